@@ -1,0 +1,142 @@
+/*
+ * ih.h -- C ABI of libih.so: exact integral histograms on AMD MI355X (gfx950).
+ *
+ * The integral histogram of a uint8 frame I with H rows, W columns and B bins
+ * is (Sec. 2.1, Eq. 1 of Poostchi et al., "Fast Integral Histogram
+ * Computations on GPU for Real-Time Video Analytics"):
+ *
+ *     H(x, y, b) = #{ (x', y') : x' <= x, y' <= y, Q(I[y'][x']) == b }
+ *
+ * for column x in [0, W), row y in [0, H), bin b in [0, B), with the binning
+ * function Q(v) = floor(v * B / 256) (the paper leaves bin edges open; these
+ * are uniform bins over the 8-bit range).  Counts are exact uint32.
+ *
+ * Tensor layout (all entry points): H x W x B, bin index innermost,
+ *     entry (x, y, b) at element offset ((size_t)y * W + x) * B + b.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an ih_status and never aborts or throws.
+ *   - Argument errors are reported before anything is launched or written.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.  The caller owns every buffer
+ *     it passes in; the library never frees caller memory.
+ *   - Asynchronous calls enqueue work on the given stream and return at once;
+ *     results are ready when the stream reaches that point.
+ *   - A stream argument is a hipStream_t passed as void*; NULL means the
+ *     null (default) stream.
+ */
+#ifndef IH_H_
+#define IH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IH_OK = 0,
+    IH_ERR_INVALID_ARG = 1,     /* null pointer, size <= 0, B outside [1,256], bad rectangle   */
+    IH_ERR_RANGE = 2,           /* H*W >= 2^32: counts or indices would not fit                */
+    IH_ERR_OOM = 3,             /* the library could not allocate its device scratch           */
+    IH_ERR_HIP = 4,             /* a HIP runtime call failed; see ih_last_error()              */
+    IH_ERR_BUDGET = 5,          /* a request exceeds the serving loop's whole HBM budget       */
+    IH_NOT_READY = 6,           /* polled work has not finished yet                            */
+    IH_ERR_UNKNOWN_TICKET = 7,  /* polled ticket was never issued or was already collected     */
+    IH_ERR_SHUTDOWN = 8         /* the server is shutting down                                 */
+} ih_status;
+
+typedef void* ih_stream_t;      /* a hipStream_t */
+
+/* A query rectangle with INCLUSIVE corners: columns x0..x1, rows y0..y1.
+ * Valid when 0 <= x0 <= x1 < W and 0 <= y0 <= y1 < H. */
+typedef struct {
+    int32_t x0, y0, x1, y1;
+} ih_rect;
+
+/* A non-owning view of an integral histogram already in device memory. */
+typedef struct {
+    const uint32_t* data;       /* device, H*W*B uint32 in the layout above */
+    int32_t H, W, B;
+    ih_stream_t stream;         /* stream the query work is enqueued on      */
+} ih_view;
+
+/*
+ * ih_compute -- the integral histogram of one frame (Sec. 2.1 Eq. 1; the
+ * sequential recursion of Sec. 2.2 Algorithm 1 gives the same result).
+ *
+ *   frame  device, H*W uint8, row-major (I[y][x] at y*W + x), read only.
+ *   H, W   rows and columns, each >= 1, with H*W < 2^32.
+ *   B      number of bins, 1..256.
+ *   out    device, >= H*W*B uint32, written completely (layout above).
+ *   stream enqueue on this stream.
+ *
+ * The library keeps a device scratch buffer per stream for its carries
+ * (about (1/TX + 1/TY) of the output size for the chosen tile); it grows on
+ * demand (the first call at a larger size synchronizes that stream) and is
+ * released at process exit.  Errors: IH_ERR_INVALID_ARG, IH_ERR_RANGE,
+ * IH_ERR_OOM, IH_ERR_HIP.
+ */
+ih_status ih_compute(const uint8_t* frame, int32_t H, int32_t W, int32_t B,
+                     uint32_t* out, ih_stream_t stream);
+
+/*
+ * ih_query -- region histograms by the four-corner rule (Sec. 2.1, Eq. 2):
+ *
+ *   h(R, b) = H(x1, y1, b) - H(x0-1, y1, b) - H(x1, y0-1, b) + H(x0-1, y0-1, b)
+ *
+ * with H = 0 at index -1, in modular uint32 arithmetic (exact, since the
+ * true count fits).
+ *
+ *   ih      view of a computed integral histogram (device data).
+ *   rects   HOST array of n rectangles; every one is validated before
+ *           anything is launched (IH_ERR_INVALID_ARG names none written).
+ *           The array is copied before the call returns.
+ *   n       number of rectangles; 0 is a no-op.
+ *   hists   device, n*B uint32; rectangle r's histogram at r*B .. r*B+B-1,
+ *           written asynchronously on ih->stream.
+ */
+ih_status ih_query(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* hists);
+
+/*
+ * ih_query_device -- as ih_query (Eq. 2), with the rectangles already in
+ * device memory.  Each rectangle is checked on the device: an invalid one
+ * gets an all-zero histogram and increments *bad_count (device uint32,
+ * accumulated, not cleared by the call; may be NULL to skip counting).
+ */
+ih_status ih_query_device(const ih_view* ih, const ih_rect* rects_dev, size_t n,
+                          uint32_t* hists, uint32_t* bad_count);
+
+/*
+ * Per-phase timing, for measurement.  While enabled, ih_compute records HIP
+ * events on its stream around each of its three phases (per-tile counts,
+ * carry scans, tile pass); ih_profile_read waits for the recorded work and
+ * returns the summed event durations.  ih_profile_enable(on) clears the
+ * totals; on = 0 stops recording.  Process-wide; adds a few microseconds of
+ * event records per frame while on.
+ */
+typedef struct {
+    double agg_ms;      /* per-tile bin counts                         */
+    double scan_ms;     /* carry scans                                  */
+    double tile_ms;     /* tile pass: binning, scans, output stores     */
+    uint64_t frames;    /* frames recorded since ih_profile_enable      */
+} ih_phase_times;
+
+ih_status ih_profile_enable(int on);
+ih_status ih_profile_read(ih_phase_times* t);
+
+/* Human-readable name of a status code (static storage). */
+const char* ih_status_str(ih_status s);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* ih_last_error(void);
+
+/* Library version string. */
+const char* ih_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IH_H_ */

@@ -9,15 +9,12 @@ library is missing.
 
 ``synth`` draws the seeded synthetic inputs and holds none of the method.
 """
+import importlib
 
 __all__ = ["binding", "synth"]
 
 
 def __getattr__(name):
-    if name == "binding":
-        from . import binding
-        return binding
-    if name == "synth":
-        from . import synth
-        return synth
+    if name in __all__:
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

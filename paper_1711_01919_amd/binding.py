@@ -1,0 +1,151 @@
+"""ctypes binding of libih.so (C ABI in include/ih.h).
+
+Argument marshalling only: tensors supply device pointers, torch streams
+supply hipStream_t handles, and every computation runs in the library's HIP
+kernels.  Importing this module raises ImportError when libih.so has not been
+built; there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+import torch
+
+LIB_PATH = Path(__file__).resolve().with_name("libih.so")
+
+IH_OK = 0
+STATUS = {
+    0: "IH_OK", 1: "IH_ERR_INVALID_ARG", 2: "IH_ERR_RANGE", 3: "IH_ERR_OOM", 4: "IH_ERR_HIP",
+    5: "IH_ERR_BUDGET", 6: "IH_NOT_READY", 7: "IH_ERR_UNKNOWN_TICKET", 8: "IH_ERR_SHUTDOWN",
+}
+
+
+class IHError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+
+
+class Rect(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_int32), ("y0", ctypes.c_int32),
+                ("x1", ctypes.c_int32), ("y1", ctypes.c_int32)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("B", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class PhaseTimes(ctypes.Structure):
+    _fields_ = [("agg_ms", ctypes.c_double), ("scan_ms", ctypes.c_double),
+                ("tile_ms", ctypes.c_double), ("frames", ctypes.c_uint64)]
+
+
+def _load() -> ctypes.CDLL:
+    if not LIB_PATH.exists():
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1711_01919_amd.build`")
+    lib = ctypes.CDLL(str(LIB_PATH))
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.ih_compute.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.ih_query.argtypes = [ctypes.POINTER(View), vp, sz, vp]
+    lib.ih_query_device.argtypes = [ctypes.POINTER(View), vp, sz, vp, vp]
+    for f in (lib.ih_compute, lib.ih_query, lib.ih_query_device):
+        f.restype = ctypes.c_int
+    lib.ih_profile_enable.argtypes = [ctypes.c_int]
+    lib.ih_profile_enable.restype = ctypes.c_int
+    lib.ih_profile_read.argtypes = [ctypes.POINTER(PhaseTimes)]
+    lib.ih_profile_read.restype = ctypes.c_int
+    lib.ih_status_str.argtypes = [ctypes.c_int]
+    lib.ih_status_str.restype = ctypes.c_char_p
+    lib.ih_last_error.restype = ctypes.c_char_p
+    lib.ih_version.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int, where: str):
+    if st != IH_OK:
+        raise IHError(st, where, lib.ih_last_error().decode())
+
+
+def _stream_handle(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def empty_ih(H: int, W: int, B: int, device="cuda") -> torch.Tensor:
+    return torch.empty((H, W, B), dtype=torch.uint32, device=device)
+
+
+def compute(frame: torch.Tensor, B: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Integral histogram (H, W, B) uint32 of a (H, W) uint8 device frame."""
+    if frame.dtype != torch.uint8 or frame.dim() != 2 or not frame.is_cuda or not frame.is_contiguous():
+        raise ValueError("frame must be a contiguous 2-D uint8 CUDA tensor")
+    H, W = frame.shape
+    if out is None:
+        out = empty_ih(H, W, B, frame.device)
+    elif out.dtype != torch.uint32 or not out.is_contiguous() or out.numel() < H * W * B:
+        raise ValueError("out must be a contiguous uint32 tensor with H*W*B elements")
+    _check(lib.ih_compute(_ptr(frame), H, W, B, _ptr(out), _stream_handle(stream)), "ih_compute")
+    return out
+
+
+def compute_raw(frame_ptr: int, H: int, W: int, B: int, out_ptr: int, stream=None) -> int:
+    """Direct pass-through of ih_compute (status code returned, not raised)."""
+    return lib.ih_compute(frame_ptr, H, W, B, out_ptr, _stream_handle(stream))
+
+
+def _view(ih: torch.Tensor, stream) -> View:
+    if ih.dtype != torch.uint32 or ih.dim() != 3 or not ih.is_cuda or not ih.is_contiguous():
+        raise ValueError("ih must be a contiguous (H, W, B) uint32 CUDA tensor")
+    H, W, B = ih.shape
+    return View(_ptr(ih), H, W, B, _stream_handle(stream))
+
+
+def query(ih: torch.Tensor, rects, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Region histograms (n, B) for host rectangles {x0, y0, x1, y1} (inclusive)."""
+    rects = np.ascontiguousarray(rects, dtype=np.int32).reshape(-1, 4)
+    v = _view(ih, stream)
+    n = rects.shape[0]
+    if out is None:
+        out = torch.empty((n, ih.shape[2]), dtype=torch.uint32, device=ih.device)
+    _check(lib.ih_query(ctypes.byref(v), rects.ctypes.data, n, _ptr(out)), "ih_query")
+    return out
+
+
+def query_device(ih: torch.Tensor, rects_dev: torch.Tensor, out: torch.Tensor | None = None,
+                 bad_count: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Region histograms for rectangles already on the device ((n, 4) int32)."""
+    if rects_dev.dtype != torch.int32 or not rects_dev.is_cuda or not rects_dev.is_contiguous():
+        raise ValueError("rects_dev must be a contiguous int32 CUDA tensor of shape (n, 4)")
+    v = _view(ih, stream)
+    n = rects_dev.numel() // 4
+    if out is None:
+        out = torch.empty((n, ih.shape[2]), dtype=torch.uint32, device=ih.device)
+    _check(lib.ih_query_device(ctypes.byref(v), _ptr(rects_dev), n, _ptr(out), _ptr(bad_count)),
+           "ih_query_device")
+    return out
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing totals) or stop per-phase event timing of ih_compute."""
+    _check(lib.ih_profile_enable(1 if on else 0), "ih_profile_enable")
+
+
+def profile_read() -> dict:
+    """Summed per-phase event durations (ms) since profile_enable(True)."""
+    t = PhaseTimes()
+    _check(lib.ih_profile_read(ctypes.byref(t)), "ih_profile_read")
+    return {"agg_ms": t.agg_ms, "scan_ms": t.scan_ms, "tile_ms": t.tile_ms, "frames": int(t.frames)}
+
+
+def version() -> str:
+    return lib.ih_version().decode()

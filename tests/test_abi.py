@@ -1,0 +1,75 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point that include/ih.h declares, and rejects bad arguments before touching
+the device (no call here reaches a kernel)."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parent.parent
+HEADER = ROOT / "include" / "ih.h"
+LIB = ROOT / "paper_1711_01919_amd" / "libih.so"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(ih_[a-z0-9_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not LIB.exists():
+        import paper_1711_01919_amd.build as b
+        b.build()
+    return ctypes.CDLL(str(LIB))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("ih_compute", "ih_query", "ih_query_device", "ih_status_str"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in ih.h but not exported"
+
+
+def test_status_strings(lib):
+    lib.ih_status_str.restype = ctypes.c_char_p
+    for code, name in enumerate(["IH_OK", "IH_ERR_INVALID_ARG", "IH_ERR_RANGE", "IH_ERR_OOM", "IH_ERR_HIP",
+                                 "IH_ERR_BUDGET", "IH_NOT_READY", "IH_ERR_UNKNOWN_TICKET", "IH_ERR_SHUTDOWN"]):
+        assert lib.ih_status_str(code).decode() == name
+
+
+def test_compute_rejects_bad_arguments_before_launch(lib):
+    f = lib.ih_compute
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    fake = 0x1000  # never dereferenced: validation fails first
+    assert f(None, 4, 4, 8, fake, None) == 1
+    assert f(fake, 4, 4, 8, None, None) == 1
+    assert f(fake, 0, 4, 8, fake, None) == 1
+    assert f(fake, 4, -1, 8, fake, None) == 1
+    assert f(fake, 4, 4, 0, fake, None) == 1
+    assert f(fake, 4, 4, 257, fake, None) == 1
+    assert f(fake, 65536, 65536, 8, fake, None) == 2          # H*W = 2^32
+    assert f(fake, 4, 4, 8, fake + 2, None) == 1              # misaligned output
+
+
+class View(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("B", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+def test_query_rejects_bad_rectangles_before_launch(lib):
+    f = lib.ih_query
+    f.argtypes = [ctypes.POINTER(View), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    v = View(0x1000, 10, 20, 4, None)
+    for bad in ([0, 0, 20, 0], [-1, 0, 0, 0], [3, 0, 2, 0], [0, 5, 0, 4], [0, 0, 0, 10]):
+        rects = (ctypes.c_int32 * 8)(0, 0, 19, 9, *bad)
+        assert f(ctypes.byref(v), ctypes.addressof(rects), 2, 0x2000) == 1
+    assert f(None, None, 1, 0x2000) == 1
+    assert f(ctypes.byref(v), None, 0, None) == 0              # n = 0 is a no-op
