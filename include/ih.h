@@ -108,10 +108,71 @@ ih_status ih_query(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* 
 ih_status ih_query_device(const ih_view* ih, const ih_rect* rects_dev, size_t n,
                           uint32_t* hists, uint32_t* bad_count);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many frames of uneven size and bin count, one launch per
+ * phase for all of them, captured once in a hipGraph and replayed.
+ * ------------------------------------------------------------------------- */
+
+/* One frame of a batch: device pointers owned by the caller, which must stay
+ * valid (and keep their addresses) for the life of the plan. */
+typedef struct {
+    const uint8_t* frame;       /* device, H*W uint8, row-major              */
+    uint32_t* out;              /* device, H*W*B uint32 (layout above)        */
+    int32_t H, W, B;
+} ih_frame_desc;
+
+typedef struct {
+    int32_t autotune;       /* 1: time candidate tiles per (H, W, B) class on the
+                               plan's own buffers at creation (results cached per
+                               process and, if IH_AUTOTUNE_CACHE names a file, on
+                               disk); 0: built-in heuristic                         */
+    int32_t use_graph;      /* 1: capture the launches in hipGraphs (default)        */
+    int32_t tile_x, tile_y; /* both > 0: force this tile on every frame              */
+    int32_t nontemporal;    /* -1: as chosen; 0: regular stores; 1: non-temporal     */
+} ih_batch_options;
+
+typedef struct ih_batch_plan ih_batch_plan;
+
+typedef struct {
+    int64_t frames;          /* frames in the plan                                  */
+    int64_t entries;         /* sum of H*W*B                                        */
+    int32_t kernel_launches; /* kernels per plan launch (all phases)                */
+    int32_t tile_launches;   /* of which tile-pass kernels (one per kernel variant) */
+    int32_t graph;           /* 1 if replayed from a hipGraph                        */
+} ih_batch_info;
+
 /*
- * Per-phase timing, for measurement.  While enabled, ih_compute records HIP
- * events on its stream around each of its three phases (per-tile counts,
- * carry scans, tile pass); ih_profile_read waits for the recorded work and
+ * ih_batch_plan_create -- plan the integral histograms (Sec. 2.1 Eq. 1) of n
+ * frames.  Validates every descriptor (same rules as ih_compute), picks a tile
+ * per frame (autotuned, forced or heuristic), allocates the plan's device
+ * scratch (about (1/TX + 1/TY) of the total output) and job tables, and
+ * captures the launches.  Autotuning runs candidate launches on `stream`,
+ * writing the frames' outputs, and synchronizes it.  opt may be NULL
+ * (defaults: no autotune, graph on, heuristic tiles).
+ * Errors: IH_ERR_INVALID_ARG, IH_ERR_RANGE, IH_ERR_OOM, IH_ERR_HIP.
+ */
+ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_batch_options* opt,
+                               ih_stream_t stream, ih_batch_plan** plan);
+
+/* Enqueue every frame's integral histogram on `stream` (one graph launch; one
+ * per phase while ih_profile_enable is on).  Plans may be launched repeatedly;
+ * launches of one plan on different streams must not overlap. */
+ih_status ih_batch_plan_launch(ih_batch_plan* plan, ih_stream_t stream);
+
+/* Synchronizes the device, then frees the plan's scratch, tables and graphs. */
+ih_status ih_batch_plan_destroy(ih_batch_plan* plan);
+
+ih_status ih_batch_plan_info(const ih_batch_plan* plan, ih_batch_info* info);
+
+/* The tile chosen for frame k of the plan. */
+ih_status ih_batch_plan_frame_tile(const ih_batch_plan* plan, size_t k, int32_t* tile_x,
+                                   int32_t* tile_y, int32_t* nontemporal);
+
+/*
+ * Per-phase timing, for measurement.  While enabled, ih_compute and
+ * ih_batch_plan_launch record HIP events on their stream around each of the
+ * three phases (per-tile counts, carry scans, tile pass); ih_profile_read
+ * waits for the recorded work and
  * returns the summed event durations.  ih_profile_enable(on) clears the
  * totals; on = 0 stops recording.  Process-wide; adds a few microseconds of
  * event records per frame while on.

@@ -8,12 +8,14 @@ built; there is no fallback of any kind.
 from __future__ import annotations
 
 import ctypes
+import os
 from pathlib import Path
 
 import numpy as np
 import torch
 
-LIB_PATH = Path(__file__).resolve().with_name("libih.so")
+# IH_LIBRARY may name another build of the same library (for A/B timing).
+LIB_PATH = Path(os.environ.get("IH_LIBRARY", Path(__file__).resolve().with_name("libih.so")))
 
 IH_OK = 0
 STATUS = {
@@ -43,6 +45,21 @@ class PhaseTimes(ctypes.Structure):
                 ("tile_ms", ctypes.c_double), ("frames", ctypes.c_uint64)]
 
 
+class FrameDesc(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_void_p), ("out", ctypes.c_void_p), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("B", ctypes.c_int32)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_int64), ("entries", ctypes.c_int64), ("kernel_launches", ctypes.c_int32),
+                ("tile_launches", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
 def _load() -> ctypes.CDLL:
     if not LIB_PATH.exists():
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1711_01919_amd.build`")
@@ -57,6 +74,16 @@ def _load() -> ctypes.CDLL:
     lib.ih_profile_enable.restype = ctypes.c_int
     lib.ih_profile_read.argtypes = [ctypes.POINTER(PhaseTimes)]
     lib.ih_profile_read.restype = ctypes.c_int
+    lib.ih_batch_plan_create.argtypes = [ctypes.POINTER(FrameDesc), sz, ctypes.POINTER(BatchOptions), vp,
+                                         ctypes.POINTER(vp)]
+    lib.ih_batch_plan_launch.argtypes = [vp, vp]
+    lib.ih_batch_plan_destroy.argtypes = [vp]
+    lib.ih_batch_plan_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    lib.ih_batch_plan_frame_tile.argtypes = [vp, sz, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                             ctypes.POINTER(i32)]
+    for f in (lib.ih_batch_plan_create, lib.ih_batch_plan_launch, lib.ih_batch_plan_destroy,
+              lib.ih_batch_plan_info, lib.ih_batch_plan_frame_tile):
+        f.restype = ctypes.c_int
     lib.ih_status_str.argtypes = [ctypes.c_int]
     lib.ih_status_str.restype = ctypes.c_char_p
     lib.ih_last_error.restype = ctypes.c_char_p
@@ -133,6 +160,59 @@ def query_device(ih: torch.Tensor, rects_dev: torch.Tensor, out: torch.Tensor | 
     _check(lib.ih_query_device(ctypes.byref(v), _ptr(rects_dev), n, _ptr(out), _ptr(bad_count)),
            "ih_query_device")
     return out
+
+
+class BatchPlan:
+    """A batched integral-histogram plan over (frame, out) device tensor pairs.
+
+    The tensors must stay alive and in place while the plan exists; the plan
+    keeps references to them."""
+
+    def __init__(self, frames, outs, bins, autotune=False, use_graph=True, tile=None,
+                 nontemporal=-1, stream=None):
+        if not (len(frames) == len(outs) == len(bins)) or len(frames) == 0:
+            raise ValueError("frames, outs and bins must be equally long and non-empty")
+        descs = (FrameDesc * len(frames))()
+        for k, (f, o, b) in enumerate(zip(frames, outs, bins)):
+            if f.dtype != torch.uint8 or f.dim() != 2 or not f.is_cuda or not f.is_contiguous():
+                raise ValueError(f"frame {k} must be a contiguous 2-D uint8 CUDA tensor")
+            H, W = f.shape
+            if o.dtype != torch.uint32 or not o.is_cuda or not o.is_contiguous() or o.numel() < H * W * b:
+                raise ValueError(f"out {k} must be a contiguous uint32 CUDA tensor with H*W*B elements")
+            descs[k] = FrameDesc(_ptr(f), _ptr(o), H, W, int(b))
+        tx, ty = tile if tile else (0, 0)
+        opt = BatchOptions(1 if autotune else 0, 1 if use_graph else 0, tx, ty, int(nontemporal))
+        h = ctypes.c_void_p()
+        _check(lib.ih_batch_plan_create(descs, len(frames), ctypes.byref(opt), _stream_handle(stream),
+                                        ctypes.byref(h)), "ih_batch_plan_create")
+        self._h = h
+        self._keep = (list(frames), list(outs))
+
+    def launch(self, stream=None):
+        _check(lib.ih_batch_plan_launch(self._h, _stream_handle(stream)), "ih_batch_plan_launch")
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        _check(lib.ih_batch_plan_info(self._h, ctypes.byref(i)), "ih_batch_plan_info")
+        return {"frames": i.frames, "entries": i.entries, "kernel_launches": i.kernel_launches,
+                "tile_launches": i.tile_launches, "graph": bool(i.graph)}
+
+    def frame_tile(self, k: int):
+        tx, ty, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.ih_batch_plan_frame_tile(self._h, k, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(nt)),
+               "ih_batch_plan_frame_tile")
+        return tx.value, ty.value, bool(nt.value)
+
+    def close(self):
+        if self._h:
+            _check(lib.ih_batch_plan_destroy(self._h), "ih_batch_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on: bool = True):

@@ -34,6 +34,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 SOURCES = {
     "ih_kernels.hip": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_capi.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_batch.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_util.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
 }
 
 

@@ -1,0 +1,462 @@
+// Batched integral histograms: many frames of uneven size and bin count in
+// one launch per phase, captured in a hipGraph, with an autotuner that picks
+// the tile shape and store flavour per (H, W, B) class by timing candidates.
+#include "ih.h"
+#include "ih_internal.h"
+#include "ih_util.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace {
+
+using ih::fail;
+using ih::hip_fail;
+
+// One kernel launch of a plan.
+struct Launch {
+    enum Kind { kAgg, kScanA, kScanB, kTile } kind;
+    int tx = 64;                 // kAgg: tile width of the frames it covers
+    ih::TileVariant v{};         // kTile
+    const ih::Job* jobs = nullptr;
+    int32_t njobs = 0;
+    int64_t n = 0;               // blocks (kAgg, kScan*) or work items (kTile)
+    int32_t grid = 0;            // kTile: persistent workgroups
+};
+
+}  // namespace
+
+struct ih_batch_plan {
+    int device = 0;
+    std::vector<ih_frame_desc> descs;
+    std::vector<ih::TileChoice> tiles;
+    std::vector<ih::FrameArgs> frames;
+    void* d_scratch = nullptr;
+    void* d_tables = nullptr;
+    std::vector<Launch> launches;
+    bool use_graph = true;
+    hipGraphExec_t exec_all = nullptr;
+    hipGraphExec_t exec_phase[ih::kNumPhases] = {nullptr, nullptr, nullptr};
+    int64_t entries = 0;
+};
+
+namespace {
+
+int phase_of(const Launch& l)
+{
+    switch (l.kind) {
+    case Launch::kAgg: return 0;
+    case Launch::kScanA:
+    case Launch::kScanB: return 1;
+    default: return 2;
+    }
+}
+
+hipError_t run_launch(const ih_batch_plan* p, const Launch& l, hipStream_t s)
+{
+    const ih::FrameArgs* fr = static_cast<const ih::FrameArgs*>(p->d_tables);
+    switch (l.kind) {
+    case Launch::kAgg: return ih::launch_agg_batch(l.tx, fr, l.jobs, l.njobs, l.n, s);
+    case Launch::kScanA: return ih::launch_scan_a_batch(fr, l.jobs, l.njobs, l.n, s);
+    case Launch::kScanB: return ih::launch_scan_b_batch(fr, l.jobs, l.njobs, l.n, s);
+    case Launch::kTile: return ih::launch_tile_batch(l.v, fr, l.jobs, l.njobs, l.n, l.grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Enqueue the launches of the given phase (-1: all), in order.
+hipError_t enqueue(const ih_batch_plan* p, int phase, hipStream_t s)
+{
+    for (const Launch& l : p->launches) {
+        if (phase >= 0 && phase_of(l) != phase) continue;
+        hipError_t e = run_launch(p, l, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void free_plan(ih_batch_plan* p)
+{
+    if (!p) return;
+    if (p->exec_all) (void)hipGraphExecDestroy(p->exec_all);
+    for (auto& e : p->exec_phase)
+        if (e) (void)hipGraphExecDestroy(e);
+    if (p->d_tables) (void)hipFree(p->d_tables);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
+    delete p;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Lay out scratch and device tables, build the launch list.  Frames keep the
+// order given; tiles[k] is frame k's tile choice.
+ih_status build_plan(ih_batch_plan* p)
+{
+    const size_t n = p->descs.size();
+    // scratch
+    std::vector<size_t> off(n);
+    size_t words = 0;
+    std::vector<ih::Geom> geoms(n);
+    for (size_t k = 0; k < n; ++k) {
+        const ih_frame_desc& d = p->descs[k];
+        geoms[k] = ih::make_geom(d.H, d.W, d.B, p->tiles[k]);
+        off[k] = words;
+        words = align_up(words + ih::scratch_layout(geoms[k]).words, 64);
+        p->entries += (int64_t)d.H * d.W * d.B;
+    }
+    hipError_t e = hipMalloc(&p->d_scratch, std::max<size_t>(words * 4, 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(IH_ERR_OOM, "batch scratch of %zu bytes: %s", words * 4, hipGetErrorString(e));
+    }
+    p->frames.resize(n);
+    for (size_t k = 0; k < n; ++k)
+        p->frames[k] = ih::frame_args(p->descs[k].frame, p->descs[k].out,
+                                      static_cast<uint32_t*>(p->d_scratch) + off[k], geoms[k]);
+
+    // job tables
+    std::vector<std::vector<ih::Job>> tables;
+    std::vector<Launch> launches;
+    for (int tx : {32, 64}) {
+        std::vector<ih::Job> jobs;
+        int64_t begin = 0;
+        for (size_t k = 0; k < n; ++k) {
+            if (geoms[k].TX != tx) continue;
+            jobs.push_back(ih::Job{begin, (int32_t)k, 0, 0, 0});
+            begin += (int64_t)geoms[k].nTX * geoms[k].nTY;
+        }
+        if (jobs.empty()) continue;
+        Launch l;
+        l.kind = Launch::kAgg;
+        l.tx = tx;
+        l.n = begin;
+        l.njobs = (int32_t)jobs.size();
+        launches.push_back(l);
+        tables.push_back(std::move(jobs));
+    }
+    for (Launch::Kind kind : {Launch::kScanA, Launch::kScanB}) {
+        std::vector<ih::Job> jobs;
+        int64_t begin = 0;
+        for (size_t k = 0; k < n; ++k) {
+            const int64_t nb = kind == Launch::kScanA ? ih::scan_a_blocks(geoms[k]) : ih::scan_b_blocks(geoms[k]);
+            if (nb == 0) continue;
+            jobs.push_back(ih::Job{begin, (int32_t)k, 0, 0, 0});
+            begin += nb;
+        }
+        Launch l;
+        l.kind = kind;
+        l.n = begin;
+        l.njobs = (int32_t)jobs.size();
+        launches.push_back(l);
+        tables.push_back(std::move(jobs));
+    }
+    std::map<ih::TileVariant, std::vector<ih::Job>> byv;
+    std::map<ih::TileVariant, int64_t> items;
+    for (size_t k = 0; k < n; ++k) {
+        const ih::Geom& g = geoms[k];
+        const int32_t n_int = ih::interior_groups(g, p->descs[k].frame, p->descs[k].out);
+        const int32_t parts[2][2] = {{0, n_int}, {n_int, g.nJG - n_int}};
+        for (int q = 0; q < 2; ++q) {
+            if (parts[q][1] <= 0) continue;
+            const ih::TileVariant v = ih::tile_variant(g, p->tiles[k].nontemporal, q == 1);
+            int64_t& b = items[v];
+            byv[v].push_back(ih::Job{b, (int32_t)k, parts[q][0], parts[q][1], 0});
+            b += (int64_t)g.nTY * parts[q][1];
+        }
+    }
+    for (auto& kv : byv) {
+        Launch l;
+        l.kind = Launch::kTile;
+        l.v = kv.first;
+        l.n = items[kv.first];
+        l.njobs = (int32_t)kv.second.size();
+        const int64_t want = (l.n + ih::kWavesPerBlock - 1) / ih::kWavesPerBlock;
+        l.grid = (int32_t)std::min<int64_t>(want, ih::tile_resident_blocks(kv.first));
+        launches.push_back(l);
+        tables.push_back(std::move(kv.second));
+    }
+
+    // one device allocation: FrameArgs table, then every job table
+    size_t bytes = align_up(n * sizeof(ih::FrameArgs), 256);
+    std::vector<size_t> toff(tables.size());
+    for (size_t t = 0; t < tables.size(); ++t) {
+        toff[t] = bytes;
+        bytes = align_up(bytes + tables[t].size() * sizeof(ih::Job), 256);
+    }
+    std::vector<unsigned char> host(bytes, 0);
+    std::memcpy(host.data(), p->frames.data(), n * sizeof(ih::FrameArgs));
+    for (size_t t = 0; t < tables.size(); ++t)
+        std::memcpy(host.data() + toff[t], tables[t].data(), tables[t].size() * sizeof(ih::Job));
+    e = hipMalloc(&p->d_tables, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(IH_ERR_OOM, "batch tables: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(p->d_tables, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload batch tables");
+    for (size_t t = 0; t < tables.size(); ++t)
+        launches[t].jobs = reinterpret_cast<const ih::Job*>(static_cast<unsigned char*>(p->d_tables) + toff[t]);
+    p->launches = std::move(launches);
+    return IH_OK;
+}
+
+ih_status capture(ih_batch_plan* p, int phase, hipGraphExec_t* out)
+{
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = enqueue(p, phase, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        e = e1 != hipSuccess ? e1 : e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    return IH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int32_t H, W, B;
+    bool operator<(const TuneKey& o) const { return std::tie(H, W, B) < std::tie(o.H, o.W, o.B); }
+};
+
+struct TuneCache {
+    std::mutex mu;
+    std::map<TuneKey, ih::TileChoice> best;
+    bool loaded = false;
+};
+TuneCache& tune_cache()
+{
+    static TuneCache* c = new TuneCache;
+    return *c;
+}
+
+const char* cache_path() { return std::getenv("IH_AUTOTUNE_CACHE"); }
+
+// The cache file holds one line per class: "gfx950 H W B TX TY NT".
+void load_cache(TuneCache& c)
+{
+    if (c.loaded) return;
+    c.loaded = true;
+    const char* path = cache_path();
+    if (!path) return;
+    std::ifstream in(path);
+    std::string arch;
+    int H, W, B, TX, TY, NT;
+    while (in >> arch >> H >> W >> B >> TX >> TY >> NT) {
+        if (arch != "gfx950") continue;
+        ih::TileChoice t{TX, TY, NT != 0};
+        if (ih::tile_supported(B, t)) c.best[TuneKey{H, W, B}] = t;
+    }
+}
+
+void save_cache(TuneCache& c)
+{
+    const char* path = cache_path();
+    if (!path) return;
+    std::ofstream out(path);
+    for (auto& kv : c.best)
+        out << "gfx950 " << kv.first.H << ' ' << kv.first.W << ' ' << kv.first.B << ' ' << kv.second.TX
+            << ' ' << kv.second.TY << ' ' << (kv.second.nontemporal ? 1 : 0) << '\n';
+}
+
+std::vector<ih::TileChoice> candidates(int32_t B)
+{
+    std::vector<ih::TileChoice> c;
+    for (int tx : {32, 64})
+        for (int ty : {16, 32, 64, 128, 256})
+            for (bool nt : {false, true}) {
+                ih::TileChoice t{tx, ty, nt};
+                if (ih::tile_supported(B, t)) c.push_back(t);
+            }
+    return c;
+}
+
+// Time one candidate on the frames of a class (all phases, no graph).
+ih_status time_candidate(const std::vector<ih_frame_desc>& descs, const ih::TileChoice& t,
+                         hipStream_t s, float* ms)
+{
+    ih_batch_plan* p = new ih_batch_plan;
+    p->descs = descs;
+    p->tiles.assign(descs.size(), t);
+    p->use_graph = false;
+    ih_status st = build_plan(p);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (st == IH_OK) {
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e == hipSuccess) e = enqueue(p, -1, s);                      // warm-up
+        float best = 1e30f;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+            e = hipEventRecord(a, s);
+            if (e == hipSuccess) e = enqueue(p, -1, s);
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float m = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&m, a, b);
+            best = std::min(best, m);
+        }
+        *ms = best;
+        if (e != hipSuccess) st = hip_fail(e, "autotune run");
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (p->d_scratch || p->d_tables) (void)hipDeviceSynchronize();
+    free_plan(p);
+    return st;
+}
+
+ih_status autotune(ih_batch_plan* p, hipStream_t s)
+{
+    std::map<TuneKey, std::vector<size_t>> classes;
+    for (size_t k = 0; k < p->descs.size(); ++k)
+        classes[TuneKey{p->descs[k].H, p->descs[k].W, p->descs[k].B}].push_back(k);
+    TuneCache& c = tune_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    load_cache(c);
+    bool dirty = false;
+    for (auto& kv : classes) {
+        auto hit = c.best.find(kv.first);
+        if (hit == c.best.end()) {
+            std::vector<ih_frame_desc> descs;
+            for (size_t k : kv.second) descs.push_back(p->descs[k]);
+            ih::TileChoice best = ih::default_tile(kv.first.H, kv.first.W, kv.first.B);
+            float best_ms = 1e30f;
+            for (const ih::TileChoice& t : candidates(kv.first.B)) {
+                float ms = 0.f;
+                if (ih_status st = time_candidate(descs, t, s, &ms)) return st;
+                if (ms < best_ms) { best_ms = ms; best = t; }
+            }
+            hit = c.best.emplace(kv.first, best).first;
+            dirty = true;
+        }
+        for (size_t k : kv.second) p->tiles[k] = hit->second;
+    }
+    if (dirty) save_cache(c);
+    return IH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_batch_options* opt,
+                               ih_stream_t stream, ih_batch_plan** plan)
+{
+    if (!plan) return fail(IH_ERR_INVALID_ARG, "plan must be non-null");
+    *plan = nullptr;
+    if (n == 0 || !frames) return fail(IH_ERR_INVALID_ARG, "need at least one frame");
+    if (n > (1u << 20)) return fail(IH_ERR_RANGE, "too many frames (%zu)", n);
+    ih_batch_options o{0, 1, 0, 0, -1};
+    if (opt) o = *opt;
+    const bool forced = o.tile_x > 0 || o.tile_y > 0;
+    for (size_t k = 0; k < n; ++k) {
+        const ih_frame_desc& d = frames[k];
+        if (!d.frame || !d.out) return fail(IH_ERR_INVALID_ARG, "frame %zu: null pointer", k);
+        if (ih_status st = ih::check_shape(d.H, d.W, d.B)) return st;
+        if (reinterpret_cast<uintptr_t>(d.out) & 3u) return fail(IH_ERR_INVALID_ARG, "frame %zu: out misaligned", k);
+        if (forced && !ih::tile_supported(d.B, ih::TileChoice{o.tile_x, o.tile_y, false}))
+            return fail(IH_ERR_INVALID_ARG, "tile %dx%d not supported for B=%d", o.tile_x, o.tile_y, d.B);
+    }
+    ih_batch_plan* p = new ih_batch_plan;
+    (void)hipGetDevice(&p->device);
+    p->descs.assign(frames, frames + n);
+    p->use_graph = o.use_graph != 0;
+    p->tiles.resize(n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ih_status st = IH_OK;
+    if (forced) {
+        for (size_t k = 0; k < n; ++k) p->tiles[k] = ih::TileChoice{o.tile_x, o.tile_y, false};
+    } else if (o.autotune) {
+        st = autotune(p, s);
+    } else {
+        for (size_t k = 0; k < n; ++k) p->tiles[k] = ih::default_tile(frames[k].H, frames[k].W, frames[k].B);
+    }
+    if (st == IH_OK && o.nontemporal >= 0)
+        for (auto& t : p->tiles) t.nontemporal = o.nontemporal != 0;
+    if (st == IH_OK) st = build_plan(p);
+    if (st == IH_OK && p->use_graph) {
+        st = capture(p, -1, &p->exec_all);
+        for (int ph = 0; st == IH_OK && ph < ih::kNumPhases; ++ph) st = capture(p, ph, &p->exec_phase[ph]);
+    }
+    if (st != IH_OK) {
+        free_plan(p);
+        return st;
+    }
+    *plan = p;
+    return IH_OK;
+}
+
+ih_status ih_batch_plan_launch(ih_batch_plan* p, ih_stream_t stream)
+{
+    if (!p) return fail(IH_ERR_INVALID_ARG, "plan must be non-null");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ih::PhaseTimer timer;
+    const bool prof = ih::profiling_on();
+    if (!prof) {
+        hipError_t e = p->use_graph ? hipGraphLaunch(p->exec_all, s) : enqueue(p, -1, s);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+        return IH_OK;
+    }
+    for (int ph = 0; ph < ih::kNumPhases; ++ph) {
+        if (ih_status st = timer.begin(ph, s)) return st;
+        hipError_t e = p->use_graph ? hipGraphLaunch(p->exec_phase[ph], s) : enqueue(p, ph, s);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+        if (ih_status st = timer.end(s)) return st;
+    }
+    ih::profiling_add_frames((uint64_t)p->descs.size());
+    return IH_OK;
+}
+
+ih_status ih_batch_plan_destroy(ih_batch_plan* p)
+{
+    if (!p) return IH_OK;
+    hipError_t e = hipDeviceSynchronize();
+    free_plan(p);
+    if (e != hipSuccess) return hip_fail(e, "synchronize before destroy");
+    return IH_OK;
+}
+
+ih_status ih_batch_plan_info(const ih_batch_plan* p, ih_batch_info* info)
+{
+    if (!p || !info) return fail(IH_ERR_INVALID_ARG, "plan and info must be non-null");
+    info->frames = (int64_t)p->descs.size();
+    info->entries = p->entries;
+    info->kernel_launches = (int32_t)p->launches.size();
+    info->graph = p->use_graph ? 1 : 0;
+    int32_t tile_launches = 0;
+    for (const Launch& l : p->launches) tile_launches += l.kind == Launch::kTile;
+    info->tile_launches = tile_launches;
+    return IH_OK;
+}
+
+ih_status ih_batch_plan_frame_tile(const ih_batch_plan* p, size_t k, int32_t* tile_x, int32_t* tile_y,
+                                   int32_t* nontemporal)
+{
+    if (!p || k >= p->descs.size() || !tile_x || !tile_y || !nontemporal)
+        return fail(IH_ERR_INVALID_ARG, "bad plan, index or output pointer");
+    *tile_x = p->tiles[k].TX;
+    *tile_y = p->tiles[k].TY;
+    *nontemporal = p->tiles[k].nontemporal ? 1 : 0;
+    return IH_OK;
+}
+
+}  // extern "C"

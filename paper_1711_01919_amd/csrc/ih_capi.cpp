@@ -1,49 +1,21 @@
-// C ABI of libih.so (declared in include/ih.h): argument validation, scratch
-// management and dispatch to the HIP kernels.  No arithmetic of the method
-// happens here; every step runs on the GPU.
+// Single-frame entry points of libih.so (declared in include/ih.h): argument
+// validation, per-stream scratch and dispatch to the HIP kernels.  No
+// arithmetic of the method happens here; every step runs on the GPU.
 #include "ih.h"
 #include "ih_internal.h"
+#include "ih_util.h"
 
 #include <hip/hip_runtime.h>
 
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
+#include <cstdint>
 #include <map>
 #include <mutex>
-#include <string>
 #include <utility>
-#include <vector>
 
 namespace {
 
-thread_local std::string g_last_error;
-
-ih_status fail(ih_status st, const char* fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return st;
-}
-
-ih_status hip_fail(hipError_t e, const char* where)
-{
-    return fail(IH_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
-}
-
-// Checks shared by every entry point that takes a frame shape.
-ih_status check_shape(int32_t H, int32_t W, int32_t B)
-{
-    if (H <= 0 || W <= 0) return fail(IH_ERR_INVALID_ARG, "H=%d and W=%d must be >= 1", H, W);
-    if (B < 1 || B > 256) return fail(IH_ERR_INVALID_ARG, "B=%d must be in [1, 256]", B);
-    if ((uint64_t)H * (uint64_t)W >= (1ull << 32))
-        return fail(IH_ERR_RANGE, "H*W=%llu must be below 2^32", (unsigned long long)H * (unsigned long long)W);
-    return IH_OK;
-}
+using ih::fail;
+using ih::hip_fail;
 
 // Device scratch per (device, stream).  Work on one stream is ordered, so one
 // buffer per stream is never used by two launches at once.
@@ -89,102 +61,31 @@ ih_status get_scratch(hipStream_t stream, size_t bytes, void** out)
     return IH_OK;
 }
 
-// Per-phase event timing (off unless ih_profile_enable(1) was called).
-struct Profiler {
-    std::mutex mu;
-    bool on = false;
-    struct Rec { hipEvent_t a, b; int phase; };
-    std::vector<Rec> pending;
-    std::vector<hipEvent_t> pool;
-    double ms[ih::kNumPhases] = {0, 0, 0};
-    uint64_t frames = 0;
-
-    hipEvent_t get()
-    {
-        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-    hipError_t drain()
-    {
-        for (Rec& r : pending) {
-            hipError_t e = hipEventSynchronize(r.b);
-            if (e != hipSuccess) return e;
-            float t = 0.f;
-            e = hipEventElapsedTime(&t, r.a, r.b);
-            if (e != hipSuccess) return e;
-            ms[r.phase] += t;
-            pool.push_back(r.a);
-            pool.push_back(r.b);
-        }
-        pending.clear();
-        return hipSuccess;
-    }
-};
-Profiler& profiler()
+// The three phases of one frame on one stream, timed when profiling is on.
+ih_status enqueue_frame(const uint8_t* frame, uint32_t* out, uint32_t* scratch,
+                        const ih::Geom& g, bool nt, hipStream_t s)
 {
-    static Profiler* p = new Profiler;
-    return *p;
+    const ih::FrameArgs fa = ih::frame_args(frame, out, scratch, g);
+    ih::PhaseTimer timer;
+    for (int ph = 0; ph < ih::kNumPhases; ++ph) {
+        if (ih_status st = timer.begin(ph, s)) return st;
+        hipError_t e = ih::launch_phase(static_cast<ih::Phase>(ph), fa, nt, s);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        if (ih_status st = timer.end(s)) return st;
+    }
+    if (ih::profiling_on()) ih::profiling_add_frames(1);
+    return IH_OK;
+}
+
+ih_status check_view(const ih_view* ih)
+{
+    if (!ih || !ih->data) return fail(IH_ERR_INVALID_ARG, "view and its data must be non-null");
+    return ih::check_shape(ih->H, ih->W, ih->B);
 }
 
 }  // namespace
 
 extern "C" {
-
-ih_status ih_profile_enable(int on)
-{
-    Profiler& p = profiler();
-    std::lock_guard<std::mutex> lock(p.mu);
-    hipError_t e = p.drain();
-    if (e != hipSuccess) return hip_fail(e, "profile drain");
-    p.on = on != 0;
-    for (double& m : p.ms) m = 0;
-    p.frames = 0;
-    return IH_OK;
-}
-
-ih_status ih_profile_read(ih_phase_times* t)
-{
-    if (!t) return fail(IH_ERR_INVALID_ARG, "t must be non-null");
-    Profiler& p = profiler();
-    std::lock_guard<std::mutex> lock(p.mu);
-    hipError_t e = p.drain();
-    if (e != hipSuccess) return hip_fail(e, "profile drain");
-    t->agg_ms = p.ms[0];
-    t->scan_ms = p.ms[1];
-    t->tile_ms = p.ms[2];
-    t->frames = p.frames;
-    return IH_OK;
-}
-
-// The three phases of one frame on one stream, with optional event timing.
-static ih_status enqueue_frame(const uint8_t* frame, uint32_t* out, uint32_t* scratch,
-                               const ih::Geom& g, bool nt, hipStream_t s)
-{
-    Profiler& p = profiler();
-    std::unique_lock<std::mutex> lock(p.mu);
-    const bool prof = p.on;
-    if (!prof) lock.unlock();
-    for (int ph = 0; ph < ih::kNumPhases; ++ph) {
-        hipEvent_t a = nullptr, b = nullptr;
-        if (prof) {
-            a = p.get(); b = p.get();
-            if (!a || !b) return fail(IH_ERR_HIP, "hipEventCreate failed");
-            hipError_t e = hipEventRecord(a, s);
-            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        }
-        hipError_t e = ih::launch_phase(static_cast<ih::Phase>(ph), frame, out, scratch, g, nt, s);
-        if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        if (prof) {
-            e = hipEventRecord(b, s);
-            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-            p.pending.push_back(Profiler::Rec{a, b, ph});
-        }
-    }
-    if (prof) p.frames += 1;
-    return IH_OK;
-}
 
 const char* ih_status_str(ih_status s)
 {
@@ -202,15 +103,13 @@ const char* ih_status_str(ih_status s)
     return "IH_STATUS_UNKNOWN";
 }
 
-const char* ih_last_error(void) { return g_last_error.c_str(); }
-
-const char* ih_version(void) { return "ih 0.1 (gfx950)"; }
+const char* ih_version(void) { return "ih 0.2 (gfx950)"; }
 
 ih_status ih_compute(const uint8_t* frame, int32_t H, int32_t W, int32_t B,
                      uint32_t* out, ih_stream_t stream)
 {
     if (!frame || !out) return fail(IH_ERR_INVALID_ARG, "frame and out must be non-null");
-    if (ih_status st = check_shape(H, W, B)) return st;
+    if (ih_status st = ih::check_shape(H, W, B)) return st;
     if (reinterpret_cast<uintptr_t>(out) & 3u) return fail(IH_ERR_INVALID_ARG, "out must be 4-byte aligned");
 
     const ih::TileChoice t = ih::default_tile(H, W, B);
@@ -220,12 +119,6 @@ ih_status ih_compute(const uint8_t* frame, int32_t H, int32_t W, int32_t B,
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (ih_status st = get_scratch(s, sl.words * sizeof(uint32_t), &scratch)) return st;
     return enqueue_frame(frame, out, static_cast<uint32_t*>(scratch), g, t.nontemporal, s);
-}
-
-static ih_status check_view(const ih_view* ih)
-{
-    if (!ih || !ih->data) return fail(IH_ERR_INVALID_ARG, "view and its data must be non-null");
-    return check_shape(ih->H, ih->W, ih->B);
 }
 
 ih_status ih_query(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* hists)

@@ -1,4 +1,5 @@
-// Internal declarations shared by the kernels and the C-ABI layer of libih.
+// Internal declarations shared by the kernels, the C-ABI layer and the batch
+// planner of libih.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,6 +10,8 @@ namespace ih {
 
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kWavesPerBlock = 4;    // independent waves per workgroup in the tile pass
+constexpr int kScanThreads = 256;    // threads per block of the scan kernels
+constexpr int kAggThreads = 256;     // threads per block of the per-tile count kernel
 
 // Tile decomposition of one frame.  A tile is TY rows x TX columns.  In the
 // tile pass a wave covers S horizontally adjacent tiles ("segments"); inside a
@@ -28,8 +31,29 @@ struct Geom {
 struct ScratchLayout {
     size_t rowc, colc, corner, words;
 };
-
 ScratchLayout scratch_layout(const Geom& g);
+
+// Everything a kernel needs about one frame.
+struct FrameArgs {
+    const uint8_t* frame;
+    uint32_t* out;
+    uint32_t* rowc;
+    uint32_t* colc;
+    uint32_t* corner;
+    Geom g;
+};
+FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g);
+
+// A job maps a contiguous range of a batched launch -- blocks for the count
+// and scan kernels, work items (one per wave) for the tile kernel -- to one
+// frame.  Jobs of a launch are sorted by `begin`.
+struct Job {
+    int64_t begin;
+    int32_t frame;       // index into the FrameArgs table
+    int32_t jg_begin;    // tile pass: first column group of the job
+    int32_t jg_count;    // tile pass: column groups per tile band
+    int32_t pad;
+};
 
 // Tile choice (TX, TY, store flavour) for a frame shape.
 struct TileChoice {
@@ -37,21 +61,46 @@ struct TileChoice {
     bool nontemporal;
 };
 
+int bins_per_lane(int B);
 Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t);
 TileChoice default_tile(int32_t H, int32_t W, int32_t B);
 bool tile_supported(int32_t B, const TileChoice& t);
 
-// Column groups that run the unguarded tile kernel (the rest run the guarded one).
+// Column groups [0, n) run the unguarded tile kernel; the rest the guarded one.
 int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out);
 
-// The three phases of one frame, enqueued in this order on one stream:
-// per-tile counts, carry scans, tile pass.
+// Which compiled tile kernel serves a frame part.
+struct TileVariant {
+    int32_t bpl, tx, bc;     // bins per lane, tile width, compile-time B (0: runtime B)
+    bool nt, guard;
+    bool operator<(const TileVariant& o) const;
+    bool operator==(const TileVariant& o) const;
+};
+TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard);
+
+// ---- single frame: the three phases in order on one stream ----------------
 enum class Phase { kAgg = 0, kScan = 1, kTile = 2 };
 constexpr int kNumPhases = 3;
-hipError_t launch_phase(Phase ph, const uint8_t* frame, uint32_t* out, uint32_t* scratch,
-                        const Geom& g, bool nontemporal, hipStream_t stream);
+hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStream_t stream);
 
-// Enqueue the four-corner query kernel.
+// ---- batched launches over a device FrameArgs table ----------------------
+hipError_t launch_agg_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                            int64_t nblocks, hipStream_t stream);
+hipError_t launch_scan_a_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                               int64_t nblocks, hipStream_t stream);
+hipError_t launch_scan_b_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                               int64_t nblocks, hipStream_t stream);
+// Persistent tile launch: `grid` workgroups loop over `nitems` work items.
+hipError_t launch_tile_batch(const TileVariant& v, const FrameArgs* frames, const Job* jobs,
+                             int32_t njobs, int64_t nitems, int32_t grid, hipStream_t stream);
+// Workgroups of the tile kernel that fit on the device at once.
+int32_t tile_resident_blocks(const TileVariant& v);
+
+// Blocks of the scan kernels for one frame.
+int64_t scan_a_blocks(const Geom& g);
+int64_t scan_b_blocks(const Geom& g);
+
+// ---- region query ---------------------------------------------------------
 hipError_t launch_query(const uint32_t* ih, int32_t H, int32_t W, int32_t B,
                         const int32_t* rects, int64_t n, uint32_t* hists,
                         uint32_t* bad_count, hipStream_t stream);

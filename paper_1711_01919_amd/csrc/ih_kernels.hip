@@ -3,24 +3,27 @@
 // The integral histogram (Sec. 2.1, Eq. 1) is a 2-D inclusive prefix count
 // per bin.  It is computed by reduce-then-scan over TY x TX tiles:
 //
-//   1. agg_kernel     per tile: bin counts of every tile-row segment, of every
-//                     tile column, and of the whole tile (LDS atomics, one
-//                     pass over the uint8 pixels).
-//   2. scan kernels   exclusive scans of those counts across tiles, giving for
-//                     each tile its left carry per row, its top carry per
-//                     column, and its top-left corner count.
-//   3. tile_kernel    the hot pass: each lane owns BPL bins of one tile
-//                     segment; it bins each pixel of the row (binning is fused
-//                     here, the one-hot tensor is never stored), scans the row
-//                     in-lane, adds the row into TX column accumulators held in
-//                     VGPRs, and stores the finished H x W x B entries.
+//   1. agg     per tile: bin counts of every tile-row segment, of every tile
+//              column, and of the whole tile (LDS atomics, one pass over the
+//              uint8 pixels).
+//   2. scan    exclusive scans of those counts across tiles, giving each tile
+//              its left carry per row, its top carry per column, and its
+//              top-left corner count.
+//   3. tile    the hot pass: each lane owns BPL bins of one tile segment; it
+//              bins each pixel of the row (binning is fused here -- the
+//              one-hot tensor is never stored), scans the row in-lane, adds
+//              the row into TX column accumulators held in VGPRs, and stores
+//              the finished H x W x B entries.
 //
 // For entry (x, y, b) of a tile whose top-left pixel is (x0, y0):
 //   H(x,y,b) = corner(b) + sum_{x0<=x'<=x} top(x',b)
 //            + sum_{y0<=y'<=y} left(y',b) + local(x,y,b)
-// where top/left/corner count the pixels above / to the left / above-left of
-// the tile.  This is the inclusion-exclusion of Eq. 1 over the four regions;
-// all arithmetic is exact uint32.
+// where top/left/corner count the pixels above / left of / above-left of the
+// tile: the inclusion-exclusion of Eq. 1 over four regions, exact in uint32.
+//
+// Each phase has one per-frame body.  Single-frame kernels take the frame by
+// value; batched kernels map their blocks (or work items) to frames through a
+// sorted job table and run the same body.
 #include "ih_internal.h"
 
 namespace ih {
@@ -28,14 +31,55 @@ namespace ih {
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Every buffer the kernels touch is device (global) memory.  Pointers read
+// from a device table carry no address space, and accesses through them would
+// compile to flat instructions, which also count against the LDS/scalar
+// counter; casting to the global address space keeps them global_*.
+#define IH_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ IH_GLOBAL T* gmem(T* p)
+{
+    return (IH_GLOBAL T*)p;
+}
+
+// The frame and job tables of a batched launch are read-only for the whole
+// launch and indexed by wave-uniform values; reading them through the
+// constant address space lets them come in with scalar loads, so everything
+// derived from them (sizes, loop bounds, pointers) stays wave-uniform.
+#define IH_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const IH_CONST T* cmem(const T* p)
+{
+    return (const IH_CONST T*)p;
+}
+template <class T>
+__device__ __forceinline__ T cload(const T* table, int64_t idx)
+{
+    T v;
+    __builtin_memcpy(&v, cmem(table) + idx, sizeof(T));
+    return v;
+}
+
+// Largest job whose `begin` is <= idx (jobs sorted by begin, jobs[0].begin == 0).
+// idx is uniform across the caller's wave, so the loads stay scalar.
+__device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs, int64_t idx)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].begin <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // Phase 1: per-tile bin counts
 // ---------------------------------------------------------------------------
-constexpr int kAggThreads = 256;
 constexpr int kAggRows = 32;     // rows whose segment counts are held in LDS at once
 
 // Two 16-bit counters per LDS word: row-segment counts are <= TX and column
-// counts are <= TY, both far below 2^16, so a carry never crosses halves.
+// counts are <= TY <= 65535, so a carry never crosses halves.
 __device__ __forceinline__ void lds_inc16(uint32_t* h, uint32_t e)
 {
     atomicAdd(&h[e >> 1], 1u << ((e & 1u) << 4));
@@ -46,19 +90,14 @@ __device__ __forceinline__ uint32_t lds_get16(const uint32_t* h, uint32_t e)
 }
 
 template <int TX>
-__global__ __launch_bounds__(kAggThreads)
-void agg_kernel(const uint8_t* __restrict__ frame, Geom g,
-                uint32_t* __restrict__ rowc, uint32_t* __restrict__ colc,
-                uint32_t* __restrict__ corner)
+__device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile,
+                                         uint32_t* rowh, uint32_t* colh)
 {
-    __shared__ uint32_t rowh[kAggRows * 256 / 2];
-    __shared__ uint32_t colh[TX * 256 / 2];
     constexpr int kRowsPerPass = kAggThreads / TX;
-
+    const Geom& g = f.g;
     const int B = g.B;
-    const int tile = blockIdx.x;
-    const int i = tile / g.nTX;
-    const int j = tile - i * g.nTX;
+    const int i = (int)(tile / g.nTX);
+    const int j = (int)(tile - (int64_t)i * g.nTX);
     const int x0 = j * TX, y0 = i * g.TY;
     const int tw = min(TX, g.W - x0);
     const int th = min(g.TY, g.H - y0);
@@ -72,8 +111,9 @@ void agg_kernel(const uint8_t* __restrict__ frame, Geom g,
         for (int e = tid; e < (rows * B + 1) / 2; e += kAggThreads) rowh[e] = 0;
         __syncthreads();                  // also orders the colh clearing before the first chunk
         if (tx < tw) {
+            const IH_GLOBAL uint8_t* p = gmem(f.frame) + (size_t)(y0 + yc) * g.W + x0 + tx;
             for (int r = tr; r < rows; r += kRowsPerPass) {
-                const uint32_t v = frame[(size_t)(y0 + yc + r) * g.W + x0 + tx];
+                const uint32_t v = p[(size_t)r * g.W];
                 const uint32_t q = (v * (uint32_t)B) >> 8;
                 lds_inc16(rowh, (uint32_t)(r * B) + q);
                 lds_inc16(colh, (uint32_t)(tx * B) + q);
@@ -83,190 +123,196 @@ void agg_kernel(const uint8_t* __restrict__ frame, Geom g,
         for (int e = tid; e < rows * B; e += kAggThreads) {
             const int r = e / B;
             const int b = e - r * B;
-            rowc[((size_t)(y0 + yc + r) * g.nTX + j) * B + b] = lds_get16(rowh, (uint32_t)e);
+            gmem(f.rowc)[((size_t)(y0 + yc + r) * g.nTX + j) * B + b] = lds_get16(rowh, (uint32_t)e);
         }
         __syncthreads();
     }
     for (int e = tid; e < tw * B; e += kAggThreads)
-        colc[((size_t)i * g.W + x0) * B + e] = lds_get16(colh, (uint32_t)e);
+        gmem(f.colc)[((size_t)i * g.W + x0) * B + e] = lds_get16(colh, (uint32_t)e);
     for (int b = tid; b < B; b += kAggThreads) {
         uint32_t s = 0;
         for (int x = 0; x < tw; ++x) s += lds_get16(colh, (uint32_t)(x * B + b));
-        corner[((size_t)i * g.nTX + j) * B + b] = s;
+        gmem(f.corner)[((size_t)i * g.nTX + j) * B + b] = s;
     }
+}
+
+template <int TX>
+__global__ __launch_bounds__(kAggThreads)
+void agg_kernel(FrameArgs f)
+{
+    __shared__ uint32_t rowh[kAggRows * 256 / 2];
+    __shared__ uint32_t colh[TX * 256 / 2];
+    agg_body<TX>(f, blockIdx.x, rowh, colh);
+}
+
+template <int TX>
+__global__ __launch_bounds__(kAggThreads)
+void agg_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
+{
+    __shared__ uint32_t rowh[kAggRows * 256 / 2];
+    __shared__ uint32_t colh[TX * 256 / 2];
+    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
+    const FrameArgs f = cload(frames, jb.frame);
+    agg_body<TX>(f, (int64_t)blockIdx.x - jb.begin, rowh, colh);
 }
 
 // ---------------------------------------------------------------------------
 // Phase 2: exclusive scans of the per-tile counts
 // ---------------------------------------------------------------------------
-constexpr int kScanThreads = 256;
-
-// Row segments across tile columns, column counts across tile bands, and tile
-// totals across bands -- all independent sequences, one thread each.
-__global__ __launch_bounds__(kScanThreads)
-void scan_a_kernel(Geom g, uint32_t* __restrict__ rowc, uint32_t* __restrict__ colc,
-                   uint32_t* __restrict__ corner)
+// Exclusive scan of p[0], p[stride], ... p[(len-1)*stride] in place.  Loads of
+// a chunk are issued before its stores so that many are in flight at once.
+__device__ __forceinline__ void scan_seq(IH_GLOBAL uint32_t* p, int64_t stride, int len)
 {
-    const int64_t B = g.B;
-    int64_t t = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
-    const int64_t nrow = (int64_t)g.H * B, ncol = (int64_t)g.W * B, ntot = (int64_t)g.nTX * B;
-    uint32_t* p;
-    int64_t stride;
-    int len;
-    if (t < nrow) {
-        const int64_t y = t / B, b = t - y * B;
-        p = rowc + y * g.nTX * B + b;
-        stride = B;
-        len = g.nTX;
-    } else if ((t -= nrow) < ncol) {
-        p = colc + t;
-        stride = (int64_t)g.W * B;
-        len = g.nTY;
-    } else if ((t -= ncol) < ntot) {
-        p = corner + t;
-        stride = (int64_t)g.nTX * B;
-        len = g.nTY;
-    } else {
-        return;
-    }
+    constexpr int C = 16;
     uint32_t run = 0;
-    for (int k = 0; k < len; ++k) {
+    int k = 0;
+    for (; k + C <= len; k += C) {
+        uint32_t v[C];
+#pragma unroll
+        for (int u = 0; u < C; ++u) v[u] = p[(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < C; ++u) { p[(k + u) * stride] = run; run += v[u]; }
+    }
+    for (; k < len; ++k) {
         const uint32_t v = p[k * stride];
         p[k * stride] = run;
         run += v;
     }
 }
 
+// Row segments across tile columns, column counts across tile bands, tile
+// totals across bands -- independent sequences, one thread each.
+__device__ __forceinline__ void scan_a_body(const FrameArgs& f, int64_t t)
+{
+    const Geom& g = f.g;
+    const int64_t B = g.B;
+    const int64_t nrow = (int64_t)g.H * B, ncol = (int64_t)g.W * B, ntot = (int64_t)g.nTX * B;
+    if (t < nrow) {
+        const int64_t y = t / B, b = t - y * B;
+        scan_seq(gmem(f.rowc) + y * g.nTX * B + b, B, g.nTX);
+    } else if ((t -= nrow) < ncol) {
+        scan_seq(gmem(f.colc) + t, (int64_t)g.W * B, g.nTY);
+    } else if ((t -= ncol) < ntot) {
+        scan_seq(gmem(f.corner) + t, (int64_t)g.nTX * B, g.nTY);
+    }
+}
+
 // Band-scanned tile totals across tile columns: corner[i][j][b] becomes the
 // count of pixels above and to the left of tile (i, j).
-__global__ __launch_bounds__(kScanThreads)
-void scan_b_kernel(Geom g, uint32_t* __restrict__ corner)
+__device__ __forceinline__ void scan_b_body(const FrameArgs& f, int64_t t)
 {
+    const Geom& g = f.g;
     const int64_t B = g.B;
-    const int64_t t = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
     if (t >= (int64_t)g.nTY * B) return;
     const int64_t i = t / B, b = t - i * B;
-    uint32_t* p = corner + i * g.nTX * B + b;
-    uint32_t run = 0;
-    for (int k = 0; k < g.nTX; ++k) {
-        const uint32_t v = p[k * B];
-        p[k * B] = run;
-        run += v;
-    }
+    scan_seq(gmem(f.corner) + i * g.nTX * B + b, B, g.nTX);
+}
+
+__global__ __launch_bounds__(kScanThreads)
+void scan_a_kernel(FrameArgs f)
+{
+    scan_a_body(f, (int64_t)blockIdx.x * kScanThreads + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kScanThreads)
+void scan_b_kernel(FrameArgs f)
+{
+    scan_b_body(f, (int64_t)blockIdx.x * kScanThreads + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kScanThreads)
+void scan_a_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
+{
+    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
+    const FrameArgs f = cload(frames, jb.frame);
+    scan_a_body(f, ((int64_t)blockIdx.x - jb.begin) * kScanThreads + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kScanThreads)
+void scan_b_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
+{
+    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
+    const FrameArgs f = cload(frames, jb.frame);
+    scan_b_body(f, ((int64_t)blockIdx.x - jb.begin) * kScanThreads + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Phase 3: the tile pass (hot loop)
 // ---------------------------------------------------------------------------
 template <int BPL, bool NT>
-__device__ __forceinline__ void store_bins(uint32_t* p, const uint32_t (&v)[BPL])
+__device__ __forceinline__ void store_bins(IH_GLOBAL uint32_t* p, const uint32_t (&v)[BPL])
 {
     if constexpr (BPL == 1) {
         if constexpr (NT) __builtin_nontemporal_store(v[0], p);
         else *p = v[0];
     } else if constexpr (BPL == 2) {
         u32x2 w = {v[0], v[1]};
-        if constexpr (NT) __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(p));
-        else *reinterpret_cast<u32x2*>(p) = w;
+        if constexpr (NT) __builtin_nontemporal_store(w, reinterpret_cast<IH_GLOBAL u32x2*>(p));
+        else *reinterpret_cast<IH_GLOBAL u32x2*>(p) = w;
     } else {
         u32x4 w = {v[0], v[1], v[2], v[3]};
-        if constexpr (NT) __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(p));
-        else *reinterpret_cast<u32x4*>(p) = w;
+        if constexpr (NT) __builtin_nontemporal_store(w, reinterpret_cast<IH_GLOBAL u32x4*>(p));
+        else *reinterpret_cast<IH_GLOBAL u32x4*>(p) = w;
     }
 }
 
-struct RowArgs {
-    const uint8_t* frame;
-    uint32_t* out;
-    const uint32_t* rowc;
-    int32_t W, nTX, B, j, x0, b0, ncols;
-    bool vec_ok;
-};
-
-// Rows y0..y1-1 of one tile segment.  GUARD=false is the interior path (the
-// whole wave has full, aligned segments); GUARD=true handles ragged right
-// edges, unaligned frames and partial bin groups with per-step predicates.
-template <int BPL, int TX, bool NT, bool GUARD>
-__device__ __forceinline__ void tile_rows(const RowArgs& a, int y0, int y1,
-                                          const uint32_t (&lo)[BPL], const uint32_t (&wd)[BPL],
-                                          const bool (&bvalid)[BPL], uint32_t (&V)[BPL][TX])
+// Pixels of row y of a tile segment (TX bytes, packed four per dword) and the
+// segment's left carries for that row (pixels of row y left of the segment,
+// per bin).
+template <int BPL, int TX, bool GUARD, bool UNIFORM>
+__device__ __forceinline__ void load_row(const FrameArgs& f, int y, int j, int x0, int b0, int B,
+                                         int ncols, const bool (&bvalid)[BPL],
+                                         uint32_t (&px)[TX / 4], uint32_t (&cnt)[BPL])
 {
-    for (int y = y0; y < y1; ++y) {
-        // Left carry of this row: pixels of row y left of the segment, per bin.
-        uint32_t cnt[BPL];
-        const uint32_t* rp = a.rowc + ((size_t)y * a.nTX + a.j) * a.B + a.b0;
+    const IH_GLOBAL uint32_t* rp = gmem(f.rowc) + ((size_t)y * f.g.nTX + j) * B + b0;
 #pragma unroll
-        for (int t = 0; t < BPL; ++t) cnt[t] = bvalid[t] ? rp[t] : 0u;
-
-        uint32_t px[TX / 4];
-        const uint8_t* prow = a.frame + (size_t)y * a.W + a.x0;
-        if constexpr (!GUARD) {
+    for (int t = 0; t < BPL; ++t) cnt[t] = bvalid[t] ? rp[t] : 0u;
+    const IH_GLOBAL uint8_t* prow = gmem(f.frame) + (size_t)y * f.g.W + x0;
+    if constexpr (!GUARD && UNIFORM) {
+        // One segment per wave: every lane reads the same pixels, so read
+        // them once with scalar loads (their wait never involves the stores).
+        const IH_CONST uint8_t* crow = cmem(f.frame) + (size_t)y * f.g.W + x0;
 #pragma unroll
-            for (int q = 0; q < TX / 16; ++q) {
-                const u32x4 w = *reinterpret_cast<const u32x4*>(prow + 16 * q);
-                px[4 * q + 0] = w.x; px[4 * q + 1] = w.y;
-                px[4 * q + 2] = w.z; px[4 * q + 3] = w.w;
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < TX / 4; ++q) px[q] = 0u;
-#pragma unroll
-            for (int k = 0; k < TX; ++k)
-                if (k < a.ncols) px[k / 4] |= (uint32_t)prow[k] << (8 * (k % 4));
+        for (int q = 0; q < TX / 16; ++q) {
+            const u32x4 w = *reinterpret_cast<const IH_CONST u32x4*>(crow + 16 * q);
+            px[4 * q + 0] = w.x; px[4 * q + 1] = w.y;
+            px[4 * q + 2] = w.z; px[4 * q + 3] = w.w;
         }
-
-        uint32_t* orow = a.out + ((size_t)y * a.W + a.x0) * a.B + a.b0;
+    } else if constexpr (!GUARD) {
 #pragma unroll
-        for (int k = 0; k < TX; ++k) {
-            const uint32_t v = (px[k / 4] >> (8 * (k % 4))) & 0xFFu;
-            uint32_t o[BPL];
-#pragma unroll
-            for (int t = 0; t < BPL; ++t) {
-                cnt[t] += (v - lo[t]) < wd[t] ? 1u : 0u;      // in-lane row scan
-                V[t][k] += cnt[t];                            // column accumulation
-                o[t] = V[t][k];
-            }
-            if constexpr (!GUARD) {
-                store_bins<BPL, NT>(orow + (size_t)k * a.B, o);
-            } else if (k < a.ncols) {
-                if (a.vec_ok) {
-                    store_bins<BPL, NT>(orow + (size_t)k * a.B, o);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < BPL; ++t)
-                        if (bvalid[t]) orow[(size_t)k * a.B + t] = o[t];
-                }
-            }
+        for (int q = 0; q < TX / 16; ++q) {
+            const u32x4 w = *reinterpret_cast<const IH_GLOBAL u32x4*>(prow + 16 * q);
+            px[4 * q + 0] = w.x; px[4 * q + 1] = w.y;
+            px[4 * q + 2] = w.z; px[4 * q + 3] = w.w;
         }
+    } else {
+#pragma unroll
+        for (int q = 0; q < TX / 4; ++q) px[q] = 0u;
+#pragma unroll
+        for (int k = 0; k < TX; ++k)
+            if (k < ncols) px[k / 4] |= (uint32_t)prow[k] << (8 * (k % 4));
     }
 }
 
-// One wave per work item: tile band i (TY rows) x column group jg (S adjacent
-// tile segments).  GUARD=false requires every active segment of every launched
-// group to be TX columns wide, the frame and W 16-byte aligned, B % BPL == 0
-// and out aligned to 4*BPL bytes; the host launches GUARD=true for the rest.
+// One wave, one work item: tile band i (TY rows) x column group jg (S adjacent
+// tile segments).  GUARD=false requires every active segment to be TX columns
+// wide, the frame and W 16-byte aligned, B % BPL == 0 and out aligned to
+// 4*BPL bytes; the host routes everything else to GUARD=true.
 template <int BPL, int TX, int BC, bool NT, bool GUARD>
-__global__ __launch_bounds__(kWave * kWavesPerBlock)
-void tile_kernel(const uint8_t* __restrict__ frame, uint32_t* __restrict__ out,
-                 const uint32_t* __restrict__ rowc, const uint32_t* __restrict__ colc,
-                 const uint32_t* __restrict__ corner, Geom g, int32_t jg_begin, int32_t jg_count)
+__device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int lane)
 {
     static_assert(TX % 16 == 0, "pixel rows are loaded 16 bytes at a time");
     constexpr int LC = BC ? (BC + BPL - 1) / BPL : 1;
+    constexpr bool UNIFORM = BC != 0 && kWave / LC == 1;      // one segment per wave
+    const Geom& g = f.g;
     const int B = BC ? BC : g.B;
     const int L = BC ? LC : g.L;
     const int S = BC ? kWave / LC : g.S;
 
-    const int lane = threadIdx.x % kWave;
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (item >= (int64_t)g.nTY * jg_count) return;        // whole wave leaves together
-    const int i = (int)(item / jg_count);
-    const int jg = jg_begin + (int)(item - (int64_t)i * jg_count);
     const int s = lane / L;
     const int b0 = (lane - s * L) * BPL;
     const int j = jg * S + s;
-    const bool active = (s < S) && (j < g.nTX) && (b0 < B);
-    if (!active) return;
+    if (!((s < S) && (j < g.nTX) && (b0 < B))) return;      // idle lane
     const int x0 = j * TX;
     const int ncols = GUARD ? min(TX, g.W - x0) : TX;
     const int y0 = i * g.TY;
@@ -290,8 +336,8 @@ void tile_kernel(const uint8_t* __restrict__ frame, uint32_t* __restrict__ out,
     uint32_t V[BPL][TX];
     {
         uint32_t acc[BPL];
-        const uint32_t* cp = corner + ((size_t)i * g.nTX + j) * B + b0;
-        const uint32_t* tp = colc + ((size_t)i * g.W + x0) * B + b0;
+        const IH_GLOBAL uint32_t* cp = gmem(f.corner) + ((size_t)i * g.nTX + j) * B + b0;
+        const IH_GLOBAL uint32_t* tp = gmem(f.colc) + ((size_t)i * g.W + x0) * B + b0;
 #pragma unroll
         for (int t = 0; t < BPL; ++t) acc[t] = bvalid[t] ? cp[t] : 0u;
 #pragma unroll
@@ -305,9 +351,90 @@ void tile_kernel(const uint8_t* __restrict__ frame, uint32_t* __restrict__ out,
     }
 
     const bool vec_ok = (b0 + BPL <= B) && (B % BPL == 0) &&
-                        ((reinterpret_cast<uintptr_t>(out) & (4 * BPL - 1)) == 0);
-    RowArgs a{frame, out, rowc, g.W, g.nTX, B, j, x0, b0, ncols, vec_ok};
-    tile_rows<BPL, TX, NT, GUARD>(a, y0, y1, lo, wd, bvalid, V);
+                        ((reinterpret_cast<uintptr_t>(f.out) & (4 * BPL - 1)) == 0);
+
+    // The loads of row y+1 (pixels and left carries) are issued before the
+    // stores of row y: loads and stores share one in-order completion counter
+    // on this architecture, so waiting for a load issued after a row's stores
+    // would also wait for all of those stores to drain.  Two register sets
+    // alternate (no copies), and the prefetch row is clamped into the band so
+    // every wave runs the same control flow.
+    auto row_pass = [&](int y, const uint32_t (&px)[TX / 4], uint32_t (&cnt)[BPL]) {
+        IH_GLOBAL uint32_t* orow = gmem(f.out) + ((size_t)y * g.W + x0) * B + b0;
+#pragma unroll
+        for (int k = 0; k < TX; ++k) {
+            const uint32_t v = (px[k / 4] >> (8 * (k % 4))) & 0xFFu;
+            uint32_t o[BPL];
+#pragma unroll
+            for (int t = 0; t < BPL; ++t) {
+                cnt[t] += (v - lo[t]) < wd[t] ? 1u : 0u;      // in-lane row scan
+                V[t][k] += cnt[t];                            // column accumulation
+                o[t] = V[t][k];
+            }
+            if constexpr (!GUARD) {
+                store_bins<BPL, NT>(orow + (size_t)k * B, o);
+            } else if (k < ncols) {
+                if (vec_ok) {
+                    store_bins<BPL, NT>(orow + (size_t)k * B, o);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < BPL; ++t)
+                        if (bvalid[t]) orow[(size_t)k * B + t] = o[t];
+                }
+            }
+        }
+    };
+    uint32_t pxa[TX / 4], cnta[BPL], pxb[TX / 4], cntb[BPL];
+    load_row<BPL, TX, GUARD, UNIFORM>(f, y0, j, x0, b0, B, ncols, bvalid, pxa, cnta);
+    // Drain everything once per work item, so that inside the loop the
+    // compiler's counter bookkeeping sees only the in-loop prefetches.
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int y = y0; y < y1; y += 2) {
+        load_row<BPL, TX, GUARD, UNIFORM>(f, min(y + 1, y1 - 1), j, x0, b0, B, ncols, bvalid, pxb, cntb);
+        __builtin_amdgcn_sched_barrier(0);        // keep the prefetch ahead of the stores
+        row_pass(y, pxa, cnta);
+        if (y + 1 >= y1) break;
+        load_row<BPL, TX, GUARD, UNIFORM>(f, min(y + 2, y1 - 1), j, x0, b0, B, ncols, bvalid, pxa, cnta);
+        __builtin_amdgcn_sched_barrier(0);
+        row_pass(y + 1, pxb, cntb);
+    }
+}
+
+// Index of the calling wave within its workgroup.  The value is the same on
+// every lane of a wave, and saying so keeps what is derived from it (work
+// item, frame, loop bounds) in scalar registers.
+__device__ __forceinline__ int wave_in_block()
+{
+    return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+}
+
+template <int BPL, int TX, int BC, bool NT, bool GUARD>
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+void tile_kernel(FrameArgs f, int32_t jg_begin, int32_t jg_count)
+{
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+    if (item >= (int64_t)f.g.nTY * jg_count) return;      // whole wave leaves together
+    const int i = (int)(item / jg_count);
+    const int jg = jg_begin + (int)(item - (int64_t)i * jg_count);
+    tile_body<BPL, TX, BC, NT, GUARD>(f, i, jg, threadIdx.x % kWave);
+}
+
+// Persistent form: each wave strides over the work items of all jobs.
+template <int BPL, int TX, int BC, bool NT, bool GUARD>
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+void tile_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs,
+                       int32_t njobs, int64_t nitems)
+{
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block(); item < nitems;
+         item += stride) {
+        const Job jb = cload(jobs, find_job(cmem(jobs), njobs, item));
+        const int64_t local = item - jb.begin;
+        const int i = (int)(local / jb.jg_count);
+        const int jg = jb.jg_begin + (int)(local - (int64_t)i * jb.jg_count);
+        const FrameArgs f = cload(frames, jb.frame);
+        tile_body<BPL, TX, BC, NT, GUARD>(f, i, jg, threadIdx.x % kWave);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -330,10 +457,10 @@ void query_kernel(const uint32_t* __restrict__ ih, int32_t H, int32_t W, int32_t
     uint32_t h = 0;
     if (ok) {
         const size_t rowA = (size_t)y1 * W;               // row y1
-        const size_t rowB = (size_t)(y0 - 1) * W;          // row y0-1 (used only when y0 > 0)
         h = ih[(rowA + x1) * B + b];
         if (x0 > 0) h -= ih[(rowA + x0 - 1) * B + b];
         if (y0 > 0) {
+            const size_t rowB = (size_t)(y0 - 1) * W;      // row y0-1
             h -= ih[(rowB + x1) * B + b];
             if (x0 > 0) h += ih[(rowB + x0 - 1) * B + b];
         }
@@ -344,7 +471,7 @@ void query_kernel(const uint32_t* __restrict__ ih, int32_t H, int32_t W, int32_t
 }
 
 // ---------------------------------------------------------------------------
-// host-side launch helpers
+// host side: geometry, variants, launches
 // ---------------------------------------------------------------------------
 ScratchLayout scratch_layout(const Geom& g)
 {
@@ -356,7 +483,13 @@ ScratchLayout scratch_layout(const Geom& g)
     return s;
 }
 
-static int bins_per_lane(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
+FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g)
+{
+    const ScratchLayout sl = scratch_layout(g);
+    return FrameArgs{frame, out, scratch + sl.rowc, scratch + sl.colc, scratch + sl.corner, g};
+}
+
+int bins_per_lane(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
 
 Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t)
 {
@@ -393,44 +526,6 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B)
     return t;
 }
 
-using TileFn = void (*)(const uint8_t*, uint32_t*, const uint32_t*, const uint32_t*,
-                        const uint32_t*, Geom, int32_t, int32_t);
-
-template <int BPL, int TX, bool NT, bool GUARD>
-static TileFn pick_b(int B)
-{
-    if constexpr (BPL == 1) {
-        if (B == 16) return tile_kernel<1, TX, 16, NT, GUARD>;
-        if (B == 32) return tile_kernel<1, TX, 32, NT, GUARD>;
-        if (B == 64) return tile_kernel<1, TX, 64, NT, GUARD>;
-        return tile_kernel<1, TX, 0, NT, GUARD>;
-    } else if constexpr (BPL == 2) {
-        if (B == 128) return tile_kernel<2, TX, 128, NT, GUARD>;
-        return tile_kernel<2, TX, 0, NT, GUARD>;
-    } else {
-        if (B == 256) return tile_kernel<4, TX, 256, NT, GUARD>;
-        return tile_kernel<4, TX, 0, NT, GUARD>;
-    }
-}
-
-template <bool NT, bool GUARD>
-static TileFn pick_tile(const Geom& g)
-{
-    switch (g.BPL) {
-    case 1: return g.TX == 32 ? pick_b<1, 32, NT, GUARD>(g.B) : pick_b<1, 64, NT, GUARD>(g.B);
-    case 2: return g.TX == 32 ? pick_b<2, 32, NT, GUARD>(g.B) : pick_b<2, 64, NT, GUARD>(g.B);
-    default: return pick_b<4, 32, NT, GUARD>(g.B);
-    }
-}
-
-static TileFn pick_tile(const Geom& g, bool nt, bool guard)
-{
-    if (nt) return guard ? pick_tile<true, true>(g) : pick_tile<true, false>(g);
-    return guard ? pick_tile<false, true>(g) : pick_tile<false, false>(g);
-}
-
-// Column groups [0, n) whose active segments are all full and aligned run the
-// unguarded kernel; the rest run the guarded one.
 int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out)
 {
     const bool aligned = ((reinterpret_cast<uintptr_t>(frame) & 15) == 0) && (g.W % 16 == 0) &&
@@ -442,53 +537,179 @@ int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out
     return full_tiles / g.S;
 }
 
-static void launch_tiles(const uint8_t* frame, uint32_t* out, const uint32_t* rowc,
-                         const uint32_t* colc, const uint32_t* corner, const Geom& g,
-                         bool nt, hipStream_t stream)
+bool TileVariant::operator<(const TileVariant& o) const
 {
-    const int32_t n_int = interior_groups(g, frame, out);
-    const int32_t parts[2][2] = {{0, n_int}, {n_int, g.nJG - n_int}};
-    for (int p = 0; p < 2; ++p) {
-        const int32_t begin = parts[p][0], count = parts[p][1];
-        if (count <= 0) continue;
-        const int64_t items = (int64_t)g.nTY * count;
-        const unsigned blocks = (unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock);
-        TileFn fn = pick_tile(g, nt, p == 1);
-        hipLaunchKernelGGL(fn, dim3(blocks), dim3(kWave * kWavesPerBlock), 0, stream,
-                           frame, out, rowc, colc, corner, g, begin, count);
+    if (bpl != o.bpl) return bpl < o.bpl;
+    if (tx != o.tx) return tx < o.tx;
+    if (bc != o.bc) return bc < o.bc;
+    if (nt != o.nt) return nt < o.nt;
+    return guard < o.guard;
+}
+bool TileVariant::operator==(const TileVariant& o) const
+{
+    return bpl == o.bpl && tx == o.tx && bc == o.bc && nt == o.nt && guard == o.guard;
+}
+
+// Bin counts with a specialised kernel (compile-time B); others use runtime B.
+static int32_t const_bins(int bpl, int B)
+{
+    if (bpl == 1 && (B == 16 || B == 32 || B == 64)) return B;
+    if (bpl == 2 && B == 128) return B;
+    if (bpl == 4 && B == 256) return B;
+    return 0;
+}
+
+TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard)
+{
+    return TileVariant{g.BPL, g.TX, const_bins(g.BPL, g.B), nontemporal, guard};
+}
+
+// Table of compiled tile kernels: single-frame and batched entry per variant.
+struct TileFns {
+    const void* single;
+    const void* batch;
+};
+
+template <int BPL, int TX, int BC, bool NT, bool GUARD>
+static TileFns fns_of()
+{
+    return TileFns{reinterpret_cast<const void*>(&tile_kernel<BPL, TX, BC, NT, GUARD>),
+                   reinterpret_cast<const void*>(&tile_batch_kernel<BPL, TX, BC, NT, GUARD>)};
+}
+
+template <int BPL, int TX, bool NT, bool GUARD>
+static TileFns pick_bc(int bc)
+{
+    if constexpr (BPL == 1) {
+        if (bc == 16) return fns_of<1, TX, 16, NT, GUARD>();
+        if (bc == 32) return fns_of<1, TX, 32, NT, GUARD>();
+        if (bc == 64) return fns_of<1, TX, 64, NT, GUARD>();
+        return fns_of<1, TX, 0, NT, GUARD>();
+    } else if constexpr (BPL == 2) {
+        if (bc == 128) return fns_of<2, TX, 128, NT, GUARD>();
+        return fns_of<2, TX, 0, NT, GUARD>();
+    } else {
+        if (bc == 256) return fns_of<4, TX, 256, NT, GUARD>();
+        return fns_of<4, TX, 0, NT, GUARD>();
     }
 }
 
-hipError_t launch_phase(Phase ph, const uint8_t* frame, uint32_t* out, uint32_t* scratch,
-                        const Geom& g, bool nontemporal, hipStream_t stream)
+template <bool NT, bool GUARD>
+static TileFns pick_v(const TileVariant& v)
 {
-    const ScratchLayout sl = scratch_layout(g);
-    uint32_t* rowc = scratch + sl.rowc;
-    uint32_t* colc = scratch + sl.colc;
-    uint32_t* corner = scratch + sl.corner;
+    switch (v.bpl) {
+    case 1: return v.tx == 32 ? pick_bc<1, 32, NT, GUARD>(v.bc) : pick_bc<1, 64, NT, GUARD>(v.bc);
+    case 2: return v.tx == 32 ? pick_bc<2, 32, NT, GUARD>(v.bc) : pick_bc<2, 64, NT, GUARD>(v.bc);
+    default: return pick_bc<4, 32, NT, GUARD>(v.bc);
+    }
+}
+
+static TileFns tile_fns(const TileVariant& v)
+{
+    if (v.nt) return v.guard ? pick_v<true, true>(v) : pick_v<true, false>(v);
+    return v.guard ? pick_v<false, true>(v) : pick_v<false, false>(v);
+}
+
+int64_t scan_a_blocks(const Geom& g)
+{
+    const int64_t n = (int64_t)g.H * g.B + (int64_t)g.W * g.B + (int64_t)g.nTX * g.B;
+    return (n + kScanThreads - 1) / kScanThreads;
+}
+
+int64_t scan_b_blocks(const Geom& g)
+{
+    return ((int64_t)g.nTY * g.B + kScanThreads - 1) / kScanThreads;
+}
+
+hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStream_t stream)
+{
+    const Geom& g = f.g;
     switch (ph) {
     case Phase::kAgg: {
         const unsigned ntiles = (unsigned)g.nTX * (unsigned)g.nTY;
         if (g.TX == 32)
-            hipLaunchKernelGGL(agg_kernel<32>, dim3(ntiles), dim3(kAggThreads), 0, stream, frame, g, rowc, colc, corner);
+            hipLaunchKernelGGL(agg_kernel<32>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
         else
-            hipLaunchKernelGGL(agg_kernel<64>, dim3(ntiles), dim3(kAggThreads), 0, stream, frame, g, rowc, colc, corner);
+            hipLaunchKernelGGL(agg_kernel<64>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
         break;
     }
-    case Phase::kScan: {
-        const int64_t na = (int64_t)g.H * g.B + (int64_t)g.W * g.B + (int64_t)g.nTX * g.B;
-        hipLaunchKernelGGL(scan_a_kernel, dim3((unsigned)((na + kScanThreads - 1) / kScanThreads)),
-                           dim3(kScanThreads), 0, stream, g, rowc, colc, corner);
-        const int64_t nb = (int64_t)g.nTY * g.B;
-        hipLaunchKernelGGL(scan_b_kernel, dim3((unsigned)((nb + kScanThreads - 1) / kScanThreads)),
-                           dim3(kScanThreads), 0, stream, g, corner);
+    case Phase::kScan:
+        hipLaunchKernelGGL(scan_a_kernel, dim3((unsigned)scan_a_blocks(g)), dim3(kScanThreads), 0, stream, f);
+        hipLaunchKernelGGL(scan_b_kernel, dim3((unsigned)scan_b_blocks(g)), dim3(kScanThreads), 0, stream, f);
+        break;
+    case Phase::kTile: {
+        const int32_t n_int = interior_groups(g, f.frame, f.out);
+        const int32_t parts[2][2] = {{0, n_int}, {n_int, g.nJG - n_int}};
+        for (int p = 0; p < 2; ++p) {
+            int32_t begin = parts[p][0], count = parts[p][1];
+            if (count <= 0) continue;
+            const int64_t items = (int64_t)g.nTY * count;
+            const unsigned blocks = (unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock);
+            const TileFns fn = tile_fns(tile_variant(g, nontemporal, p == 1));
+            FrameArgs fa = f;
+            void* args[] = {&fa, &begin, &count};
+            hipError_t e = hipLaunchKernel(fn.single, dim3(blocks), dim3(kWave * kWavesPerBlock),
+                                           args, 0, stream);
+            if (e != hipSuccess) return e;
+        }
         break;
     }
-    case Phase::kTile:
-        launch_tiles(frame, out, rowc, colc, corner, g, nontemporal, stream);
-        break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_agg_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                            int64_t nblocks, hipStream_t stream)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (TX == 32)
+        hipLaunchKernelGGL(agg_batch_kernel<32>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,
+                           frames, jobs, njobs);
+    else
+        hipLaunchKernelGGL(agg_batch_kernel<64>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,
+                           frames, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_a_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                               int64_t nblocks, hipStream_t stream)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_a_batch_kernel, dim3((unsigned)nblocks), dim3(kScanThreads), 0, stream,
+                       frames, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_b_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                               int64_t nblocks, hipStream_t stream)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_b_batch_kernel, dim3((unsigned)nblocks), dim3(kScanThreads), 0, stream,
+                       frames, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_batch(const TileVariant& v, const FrameArgs* frames, const Job* jobs,
+                             int32_t njobs, int64_t nitems, int32_t grid, hipStream_t stream)
+{
+    if (nitems <= 0) return hipSuccess;
+    const TileFns fn = tile_fns(v);
+    void* args[] = {&frames, &jobs, &njobs, &nitems};
+    hipError_t e = hipLaunchKernel(fn.batch, dim3((unsigned)grid), dim3(kWave * kWavesPerBlock), args, 0, stream);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+int32_t tile_resident_blocks(const TileVariant& v)
+{
+    const TileFns fn = tile_fns(v);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn.batch, kWave * kWavesPerBlock, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
 }
 
 hipError_t launch_query(const uint32_t* ih, int32_t H, int32_t W, int32_t B,

@@ -1,0 +1,147 @@
+"""Batched form: one launch per phase over many frames, replayed from a
+hipGraph.  Every frame must equal the oracle bit for bit, for every tile the
+autotuner may pick, across graph replays, and equal the single-frame path."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ihb():
+    from paper_1711_01919_amd import binding
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return binding
+
+
+def to_dev(frames, bins):
+    fr = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in frames]
+    outs = [torch.full((f.shape[0], f.shape[1], b), 0xA5A5A5A5, dtype=torch.uint32, device="cuda")
+            for f, b in zip(frames, bins)]
+    return fr, outs
+
+
+def test_uneven_batch_small(ihb, orc):
+    """256 frames of five resolutions (scaled down 8x) and four bin counts."""
+    from paper_1711_01919_amd import synth
+    ub = synth.uneven_batch(scale=8)
+    fr, outs = to_dev(ub.frames, ub.bins)
+    plan = ihb.BatchPlan(fr, outs, ub.bins)
+    info = plan.info()
+    assert info["frames"] == 256 and info["graph"]
+    plan.launch()
+    torch.cuda.synchronize()
+    for k, (f, b) in enumerate(zip(ub.frames, ub.bins)):
+        assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(f, b)), k
+    plan.close()
+
+
+CANDIDATES = [(tx, ty, nt) for tx in (32, 64) for ty in (16, 32, 64, 128, 256) for nt in (0, 1)]
+
+
+@pytest.mark.parametrize("tx,ty,nt", CANDIDATES)
+def test_every_tile_candidate(ihb, orc, tx, ty, nt):
+    """Each tile shape and store flavour the autotuner can choose."""
+    rng = np.random.default_rng(tx * 1000 + ty + nt)
+    shapes = [(300, 257, 64), (128, 640, 32), (97, 130, 128), (64, 192, 16), (50, 70, 3), (1, 64, 7)]
+    if tx == 32:
+        shapes.append((70, 96, 256))
+    frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _ in shapes]
+    bins = [b for _, _, b in shapes]
+    fr, outs = to_dev(frames, bins)
+    plan = ihb.BatchPlan(fr, outs, bins, tile=(tx, ty), nontemporal=nt)
+    for k in range(len(frames)):
+        assert plan.frame_tile(k) == (tx, ty, bool(nt))
+    plan.launch()
+    torch.cuda.synchronize()
+    for k, (f, b) in enumerate(zip(frames, bins)):
+        assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(f, b)), (k, f.shape, b)
+    plan.close()
+
+
+def test_graph_replays_with_eager_work_between(ihb, orc):
+    rng = np.random.default_rng(21)
+    frames = [rng.integers(0, 256, size=(240, 320), dtype=np.uint8) for _ in range(5)]
+    bins = [16, 32, 64, 128, 32]
+    fr, outs = to_dev(frames, bins)
+    refs = [orc.integral_histogram(f, b) for f, b in zip(frames, bins)]
+    plan = ihb.BatchPlan(fr, outs, bins)
+    for rep in range(4):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for k in range(len(frames)):
+            assert np.array_equal(outs[k].cpu().numpy(), refs[k]), (rep, k)
+    plan.close()
+
+
+def test_profiled_and_ungraphed_launches(ihb, orc):
+    rng = np.random.default_rng(22)
+    frames = [rng.integers(0, 256, size=(200, 256), dtype=np.uint8) for _ in range(3)]
+    bins = [64, 64, 64]
+    fr, outs = to_dev(frames, bins)
+    for use_graph in (True, False):
+        plan = ihb.BatchPlan(fr, outs, bins, use_graph=use_graph)
+        ihb.profile_enable(True)
+        plan.launch()
+        ph = ihb.profile_read()
+        ihb.profile_enable(False)
+        assert ph["frames"] == 3 and ph["tile_ms"] > 0
+        torch.cuda.synchronize()
+        for k in range(3):
+            assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(frames[k], bins[k]))
+        plan.close()
+
+
+def test_autotuned_plan(ihb, orc):
+    rng = np.random.default_rng(23)
+    frames = [rng.integers(0, 256, size=(360, 640), dtype=np.uint8) for _ in range(4)]
+    bins = [32, 32, 128, 128]
+    fr, outs = to_dev(frames, bins)
+    plan = ihb.BatchPlan(fr, outs, bins, autotune=True)
+    for o in outs:
+        o.zero_()
+    plan.launch()
+    torch.cuda.synchronize()
+    for k in range(4):
+        tx, ty, _ = plan.frame_tile(k)
+        assert tx in (32, 64) and ty in (16, 32, 64, 128, 256)
+        assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(frames[k], bins[k]))
+    plan.close()
+
+
+def test_disc_sequence_batched_equals_single_and_oracle(ihb, orc):
+    """The full 64-frame 1920x1080 B=64 sequence in the launch configuration
+    the benchmark times: batched == per-frame ih_compute == oracle, frame by
+    frame."""
+    from paper_1711_01919_amd import synth
+    frames, B = synth.disc_sequence()
+    n = frames.shape[0]
+    d = torch.from_numpy(frames).cuda()
+    outs = [torch.empty((1080, 1920, B), dtype=torch.uint32, device="cuda") for _ in range(n)]
+    plan = ihb.BatchPlan([d[k] for k in range(n)], outs, [B] * n)
+    plan.launch()
+    single = torch.empty((1080, 1920, B), dtype=torch.uint32, device="cuda")
+    for k in range(n):
+        ihb.compute(d[k], B, out=single)
+        torch.cuda.synchronize()
+        assert bool(torch.equal(single.view(torch.int32), outs[k].view(torch.int32))), k
+        if k % 8 == 0 or k == n - 1:
+            assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(frames[k], B)), k
+    plan.close()
+
+
+def test_bad_descriptors_rejected(ihb):
+    f = torch.zeros((8, 8), dtype=torch.uint8, device="cuda")
+    o = torch.zeros((8, 8, 4), dtype=torch.uint32, device="cuda")
+    with pytest.raises(ihb.IHError):
+        ihb.BatchPlan([f], [o], [0])
+    with pytest.raises(ihb.IHError):
+        ihb.BatchPlan([f], [o], [4], tile=(48, 16))
+    o256 = torch.zeros((8, 8, 256), dtype=torch.uint32, device="cuda")
+    with pytest.raises(ihb.IHError):
+        ihb.BatchPlan([f], [o256], [256], tile=(64, 16))        # B > 128 needs 32-wide tiles
