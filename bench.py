@@ -13,8 +13,10 @@ resident in HBM before the timed region starts.
 Prints ONE JSON line: throughput (entries/s) of the batched step; the same
 frames through 64 plain per-frame ih_compute calls for comparison; the
 roofline of the dominant kernel (the tile pass, HBM-bound); a write-stream
-ceiling measured with a plain fill; and the single-threaded CPU oracle timed
-on a bounded sample of the same workload.
+ceiling measured with a plain fill; the serving loop's p50/p99 latency and
+throughput on a replayed 16-stream trace next to the plain per-frame path;
+and the single-threaded CPU oracle timed on a bounded sample of the batched
+workload.
 """
 from __future__ import annotations
 
@@ -40,6 +42,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the replayed 16-stream arrival trace (0: skip the serving leg)")
     return ap.parse_args()
 
 
@@ -81,15 +85,107 @@ def timed(torch, stream, fn, steps):
     return ev0.elapsed_time(ev1)
 
 
-def write_ceiling(torch, stream, gib: float = 8.0, reps: int = 5) -> float:
-    """GB/s of a plain device fill (torch's own kernel) over a buffer far larger
-    than the 256 MB last-level cache: the write-stream ceiling of the chip."""
-    n = int(gib * (1 << 30)) // 4
-    buf = torch.empty(n, dtype=torch.int32, device="cuda")
-    buf.fill_(1)
-    ms = timed(torch, stream, lambda: buf.fill_(7), reps)
-    del buf
-    return n * 4 * reps / (ms / 1e3) / 1e9
+def write_ceiling(torch, stream, gib: int = 16, reps: int = 3) -> float:
+    """GB/s of a plain streaming write of distinct values (torch's own arange
+    kernel, 2 GiB per launch) over a buffer far larger than the 256 MB
+    last-level cache: the write-stream ceiling of the chip for data that does
+    not repeat."""
+    chunk = (2 << 30) // 4
+    bufs = [torch.empty(chunk, dtype=torch.int32, device="cuda") for _ in range(gib // 2)]
+
+    def fill():
+        for b in bufs:
+            torch.arange(chunk, out=b)
+    fill()
+    ms = timed(torch, stream, fill, reps)
+    del bufs
+    return chunk * 4 * (gib // 2) * reps / (ms / 1e3) / 1e9
+
+
+def percentiles(xs):
+    a = np.sort(np.asarray(xs, dtype=np.float64))
+    return {"p50_ms": float(np.percentile(a, 50)), "p99_ms": float(np.percentile(a, 99)),
+            "mean_ms": float(a.mean()), "max_ms": float(a.max()), "n": int(a.size)}
+
+
+def serving_leg(torch, ihb, synth, seconds: float) -> dict:
+    """16 synthetic video streams with Poisson arrivals at 30-120 fps, each
+    frame followed by 256 rectangle queries, replayed open-loop on the wall
+    clock; first through the serving loop (200 GB budget), then through the
+    plain per-frame path (one host thread, FIFO: upload, ih_compute, ih_query,
+    download, synchronize).  Latency = results in host memory - scheduled
+    arrival, both on the monotonic clock the library also stamps with."""
+    specs = synth.stream_plan(duration_s=seconds)
+    pools = [synth.stream_frame_pool(100 + s, sp, pool=3) for s, sp in enumerate(specs)]
+    events = sorted((float(t), s, k) for s, sp in enumerate(specs) for k, t in enumerate(sp.arrivals))
+    entries = sum(specs[s].H * specs[s].W * specs[s].B for _, s, _ in events)
+
+    # served: a submitting thread replays the arrivals, a polling thread
+    # collects results as they finish (as a client would)
+    import threading
+    srv = ihb.Server(budget_bytes=200 << 30, max_slots=64, n_hip_streams=4, max_batch=16,
+                     pinned_bytes=4 << 30)
+    warm = srv.submit(0, pools[0][0][0], specs[0].B, pools[0][1][0])
+    srv.wait(warm)
+    tickets = [None] * len(events)
+    arrival_ns = [0] * len(events)
+    lag = []
+    submitted = threading.Semaphore(0)
+    lat_served = [0.0] * len(events)
+
+    def poller():
+        for i in range(len(events)):
+            submitted.acquire()
+            _, tm = srv.wait(tickets[i], timeout_s=120.0, sleep_s=2e-5)
+            lat_served[i] = (tm["t_done_ns"] - arrival_ns[i]) / 1e6
+
+    th = threading.Thread(target=poller)
+    th.start()
+    t0 = time.monotonic_ns()
+    for i, (t_arr, s, k) in enumerate(events):
+        due = t0 + int(t_arr * 1e9)
+        now = time.monotonic_ns()
+        if now < due:
+            time.sleep((due - now) / 1e9)
+        arrival_ns[i] = due
+        lag.append((time.monotonic_ns() - due) / 1e6)
+        f, r = pools[s][0][k % len(pools[s][0])], pools[s][1][k % len(pools[s][1])]
+        tickets[i] = srv.submit(s, f, specs[s].B, r)
+        submitted.release()
+    th.join()
+    wall_served = (time.monotonic_ns() - t0) / 1e9
+    stats = srv.stats()
+    srv.close()
+
+    # plain per-frame path
+    dev = torch.device("cuda:0")
+    outs = {}
+    for sp in specs:
+        key = (sp.H, sp.W, sp.B)
+        if key not in outs:
+            outs[key] = torch.empty(key, dtype=torch.uint32, device=dev)
+    lat_plain = []
+    t0 = time.monotonic_ns()
+    for t_arr, s, k in events:
+        due = t0 + int(t_arr * 1e9)
+        now = time.monotonic_ns()
+        if now < due:
+            time.sleep((due - now) / 1e9)
+        sp = specs[s]
+        f = torch.from_numpy(pools[s][0][k % len(pools[s][0])]).to(dev)
+        ih = ihb.compute(f, sp.B, out=outs[(sp.H, sp.W, sp.B)])
+        h = ihb.query(ih, pools[s][1][k % len(pools[s][1])]).cpu()
+        lat_plain.append((time.monotonic_ns() - due) / 1e6)
+    wall_plain = (time.monotonic_ns() - t0) / 1e9
+    del outs
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{len(specs)} streams, {len(events)} frames over {seconds:.0f} s, 256 queries per frame",
+        "served": {**percentiles(lat_served), "entries_per_s": entries / wall_served,
+                   "submit_lag_p99_ms": float(np.percentile(np.asarray(lag), 99)),
+                   "device_bytes_peak": stats["device_bytes_peak"], "budget_blocked": stats["budget_blocked"]},
+        "plain_loop": {**percentiles(lat_plain), "entries_per_s": entries / wall_plain},
+    }
 
 
 def main():
@@ -161,6 +257,14 @@ def main():
     ceiling = write_ceiling(torch, stream)
     log(f"[bench] write-stream ceiling (fill): {ceiling:.0f} GB/s")
 
+    plan.close()
+    del outs, plan
+    torch.cuda.empty_cache()
+    served = None
+    if args.serve_seconds > 0:
+        served = serving_leg(torch, ihb, synth, args.serve_seconds)
+        log(f"[bench] serving: {served}")
+
     rec = {
         "metric": METRIC, "value": value, "unit": "entries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -178,9 +282,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "alg_bytes_per_launch": alg_bytes_launch},
     }
+    if served is not None:
+        rec["serving"] = served
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(frames, B, args.cpu_seconds)
-    plan.close()
     print(json.dumps(rec), flush=True)
 
 

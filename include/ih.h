@@ -168,6 +168,85 @@ ih_status ih_batch_plan_info(const ih_batch_plan* plan, ih_batch_info* info);
 ih_status ih_batch_plan_frame_tile(const ih_batch_plan* plan, size_t k, int32_t* tile_x,
                                    int32_t* tile_y, int32_t* nontemporal);
 
+/* ---------------------------------------------------------------------------
+ * Served form: frame + region-query requests from many video streams.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* device memory the server may hold: resident integral
+                                   histograms, uploaded frames, rectangles, results and
+                                   carries (reserved as one allocation on first use)      */
+    int32_t max_slots;          /* requests admitted and not yet finished, at most        */
+    int32_t n_hip_streams;      /* HIP streams the work is spread over (1..16)            */
+    int32_t max_batch;          /* frames per dispatched batch, at most                   */
+    int32_t retain;             /* 1: keep each video stream's latest integral histogram
+                                   resident (evicted oldest-first when memory is needed)  */
+    uint64_t pinned_bytes;      /* pinned host staging for frames, rectangles and results,
+                                   allocated on first submit (0: 1 GiB); requests that do
+                                   not fit it use separately allocated pinned buffers      */
+} ih_server_config;
+
+typedef struct {
+    uint64_t t_submit_ns;       /* ih_submit entered                                       */
+    uint64_t t_admit_ns;        /* device memory reserved, request joined a batch           */
+    uint64_t t_done_ns;         /* results in host memory, seen by the scheduler            */
+} ih_timing;                    /* steady-clock nanoseconds                                 */
+
+typedef struct ih_server ih_server;
+
+typedef struct {
+    int64_t pending;            /* submitted, waiting for admission                        */
+    int64_t admitted;           /* admitted, not yet finished                              */
+    int64_t retained;           /* resident integral histograms kept for later queries     */
+    uint64_t device_bytes_used; /* of the budget, now                                      */
+    uint64_t device_bytes_peak; /* of the budget, highest so far                           */
+    uint64_t budget_blocked;    /* times the head request waited for device memory         */
+} ih_server_counters;
+
+/*
+ * ih_server_create -- start a serving loop (a scheduler thread; device memory
+ * and streams are set up on the first request, on the device current here).
+ * Requests are admitted first-in first-out while the budget and slots allow;
+ * requests that arrive while others run join the next batch as a stream frees
+ * up (continuous batching), and batches on different streams overlap.
+ */
+ih_status ih_server_create(const ih_server_config* cfg, ih_server** server);
+
+/*
+ * ih_submit -- queue one frame (HOST memory, H*W uint8) of video stream
+ * `stream_id` and nq rectangles (HOST) to answer on it by Eq. 2.  Both arrays
+ * are copied before the call returns.  Returns a ticket for ih_poll.
+ * Errors: IH_ERR_INVALID_ARG (shape, rectangle), IH_ERR_RANGE, IH_ERR_BUDGET
+ * (the request alone exceeds the whole budget; smaller requests wait instead),
+ * IH_ERR_SHUTDOWN, IH_ERR_OOM (pinned host staging).
+ */
+ih_status ih_submit(ih_server* server, int32_t stream_id, const uint8_t* frame_host, int32_t H, int32_t W,
+                    int32_t B, const ih_rect* rects_host, size_t nq, uint64_t* ticket);
+
+/*
+ * ih_poll -- IH_NOT_READY until the request has finished; then copies its
+ * nq*B histograms to hists_host (HOST, may be NULL), fills *t (may be NULL),
+ * forgets the ticket and returns the request's status.  Unknown or already
+ * collected tickets give IH_ERR_UNKNOWN_TICKET.
+ */
+ih_status ih_poll(ih_server* server, uint64_t ticket, uint32_t* hists_host, ih_timing* t);
+
+/* Eq. 2 queries on the latest resident integral histogram of a video stream
+ * (servers created with retain = 1); blocks until the results are in
+ * hists_host.  *frame_ticket (may be NULL) names the frame it belongs to. */
+ih_status ih_server_query_latest(ih_server* server, int32_t stream_id, const ih_rect* rects_host,
+                                 size_t nq, uint32_t* hists_host, uint64_t* frame_ticket);
+
+ih_status ih_server_stats(ih_server* server, ih_server_counters* counters);
+
+/* hold = 1: keep queueing requests but admit none (e.g. to drain the device
+ * or to collect a burst); hold = 0: resume admission. */
+ih_status ih_server_hold(ih_server* server, int32_t hold);
+
+/* Stops admitting, fails still-pending requests with IH_ERR_SHUTDOWN, waits
+ * for running batches, frees everything. */
+ih_status ih_server_destroy(ih_server* server);
+
 /*
  * Per-phase timing, for measurement.  While enabled, ih_compute and
  * ih_batch_plan_launch record HIP events on their stream around each of the

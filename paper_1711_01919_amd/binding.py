@@ -60,6 +60,22 @@ class BatchInfo(ctypes.Structure):
                 ("tile_launches", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
+                ("n_hip_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("retain", ctypes.c_int32),
+                ("pinned_bytes", ctypes.c_uint64)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int64), ("admitted", ctypes.c_int64), ("retained", ctypes.c_int64),
+                ("device_bytes_used", ctypes.c_uint64), ("device_bytes_peak", ctypes.c_uint64),
+                ("budget_blocked", ctypes.c_uint64)]
+
+
 def _load() -> ctypes.CDLL:
     if not LIB_PATH.exists():
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1711_01919_amd.build`")
@@ -83,6 +99,16 @@ def _load() -> ctypes.CDLL:
                                              ctypes.POINTER(i32)]
     for f in (lib.ih_batch_plan_create, lib.ih_batch_plan_launch, lib.ih_batch_plan_destroy,
               lib.ih_batch_plan_info, lib.ih_batch_plan_frame_tile):
+        f.restype = ctypes.c_int
+    lib.ih_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.ih_submit.argtypes = [vp, i32, vp, i32, i32, i32, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
+    lib.ih_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(Timing)]
+    lib.ih_server_query_latest.argtypes = [vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_uint64)]
+    lib.ih_server_stats.argtypes = [vp, ctypes.POINTER(ServerCounters)]
+    lib.ih_server_destroy.argtypes = [vp]
+    lib.ih_server_hold.argtypes = [vp, i32]
+    for f in (lib.ih_server_create, lib.ih_submit, lib.ih_poll, lib.ih_server_query_latest,
+              lib.ih_server_stats, lib.ih_server_destroy, lib.ih_server_hold):
         f.restype = ctypes.c_int
     lib.ih_status_str.argtypes = [ctypes.c_int]
     lib.ih_status_str.restype = ctypes.c_char_p
@@ -206,6 +232,90 @@ class BatchPlan:
     def close(self):
         if self._h:
             _check(lib.ih_batch_plan_destroy(self._h), "ih_batch_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+IH_NOT_READY = 6
+
+
+class Server:
+    """Serving loop over host frames and rectangles (ih_server_* in ih.h)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, n_hip_streams: int = 4,
+                 max_batch: int = 16, retain: bool = False, pinned_bytes: int = 0):
+        cfg = ServerConfig(int(budget_bytes), max_slots, n_hip_streams, max_batch, 1 if retain else 0,
+                           int(pinned_bytes))
+        h = ctypes.c_void_p()
+        _check(lib.ih_server_create(ctypes.byref(cfg), ctypes.byref(h)), "ih_server_create")
+        self._h = h
+        self._shape = {}
+
+    def submit(self, stream_id: int, frame: np.ndarray, B: int, rects=None) -> int:
+        frame = np.ascontiguousarray(frame, dtype=np.uint8)
+        if frame.ndim != 2:
+            raise ValueError("frame must be 2-D")
+        H, W = frame.shape
+        r = np.ascontiguousarray(rects if rects is not None else np.zeros((0, 4)), dtype=np.int32).reshape(-1, 4)
+        t = ctypes.c_uint64()
+        _check(lib.ih_submit(self._h, stream_id, frame.ctypes.data, H, W, B,
+                             r.ctypes.data if len(r) else None, len(r), ctypes.byref(t)), "ih_submit")
+        self._shape[t.value] = (len(r), B)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(hists, timing) when finished, None while not ready; raises on failure."""
+        nq, B = self._shape.get(ticket, (0, 1))
+        out = np.empty((nq, B), dtype=np.uint32)
+        tm = Timing()
+        st = lib.ih_poll(self._h, ticket, out.ctypes.data if nq else None, ctypes.byref(tm))
+        if st == IH_NOT_READY:
+            return None
+        self._shape.pop(ticket, None)
+        _check(st, "ih_poll")
+        return out, {"t_submit_ns": tm.t_submit_ns, "t_admit_ns": tm.t_admit_ns, "t_done_ns": tm.t_done_ns}
+
+    def poll_status(self, ticket: int) -> int:
+        """Raw status of ih_poll (collects the ticket when finished)."""
+        return lib.ih_poll(self._h, ticket, None, None)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0, sleep_s: float = 1e-4):
+        import time
+        t_end = time.monotonic() + timeout_s
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"ticket {ticket} not finished after {timeout_s} s")
+            time.sleep(sleep_s)
+
+    def query_latest(self, stream_id: int, rects, B: int):
+        r = np.ascontiguousarray(rects, dtype=np.int32).reshape(-1, 4)
+        out = np.empty((len(r), B), dtype=np.uint32)
+        t = ctypes.c_uint64()
+        _check(lib.ih_server_query_latest(self._h, stream_id, r.ctypes.data, len(r), out.ctypes.data,
+                                          ctypes.byref(t)), "ih_server_query_latest")
+        return out, t.value
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(lib.ih_server_stats(self._h, ctypes.byref(c)), "ih_server_stats")
+        return {"pending": c.pending, "admitted": c.admitted, "retained": c.retained,
+                "device_bytes_used": c.device_bytes_used, "device_bytes_peak": c.device_bytes_peak,
+                "budget_blocked": c.budget_blocked}
+
+    def hold(self, on: bool = True):
+        _check(lib.ih_server_hold(self._h, 1 if on else 0), "ih_server_hold")
+
+    def close(self):
+        if self._h:
+            _check(lib.ih_server_destroy(self._h), "ih_server_destroy")
             self._h = None
 
     def __del__(self):

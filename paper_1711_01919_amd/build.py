@@ -36,6 +36,8 @@ SOURCES = {
     "ih_capi.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_batch.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_util.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_launch.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_server.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
 }
 
 

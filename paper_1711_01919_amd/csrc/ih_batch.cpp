@@ -3,6 +3,7 @@
 // the tile shape and store flavour per (H, W, B) class by timing candidates.
 #include "ih.h"
 #include "ih_internal.h"
+#include "ih_launch.h"
 #include "ih_util.h"
 
 #include <hip/hip_runtime.h>
@@ -24,27 +25,15 @@ namespace {
 using ih::fail;
 using ih::hip_fail;
 
-// One kernel launch of a plan.
-struct Launch {
-    enum Kind { kAgg, kScanA, kScanB, kTile } kind;
-    int tx = 64;                 // kAgg: tile width of the frames it covers
-    ih::TileVariant v{};         // kTile
-    const ih::Job* jobs = nullptr;
-    int32_t njobs = 0;
-    int64_t n = 0;               // blocks (kAgg, kScan*) or work items (kTile)
-    int32_t grid = 0;            // kTile: persistent workgroups
-};
-
 }  // namespace
 
 struct ih_batch_plan {
     int device = 0;
     std::vector<ih_frame_desc> descs;
     std::vector<ih::TileChoice> tiles;
-    std::vector<ih::FrameArgs> frames;
     void* d_scratch = nullptr;
-    void* d_tables = nullptr;
-    std::vector<Launch> launches;
+    void* d_image = nullptr;
+    ih::BatchImage image;
     bool use_graph = true;
     hipGraphExec_t exec_all = nullptr;
     hipGraphExec_t exec_phase[ih::kNumPhases] = {nullptr, nullptr, nullptr};
@@ -53,37 +42,10 @@ struct ih_batch_plan {
 
 namespace {
 
-int phase_of(const Launch& l)
-{
-    switch (l.kind) {
-    case Launch::kAgg: return 0;
-    case Launch::kScanA:
-    case Launch::kScanB: return 1;
-    default: return 2;
-    }
-}
-
-hipError_t run_launch(const ih_batch_plan* p, const Launch& l, hipStream_t s)
-{
-    const ih::FrameArgs* fr = static_cast<const ih::FrameArgs*>(p->d_tables);
-    switch (l.kind) {
-    case Launch::kAgg: return ih::launch_agg_batch(l.tx, fr, l.jobs, l.njobs, l.n, s);
-    case Launch::kScanA: return ih::launch_scan_a_batch(fr, l.jobs, l.njobs, l.n, s);
-    case Launch::kScanB: return ih::launch_scan_b_batch(fr, l.jobs, l.njobs, l.n, s);
-    case Launch::kTile: return ih::launch_tile_batch(l.v, fr, l.jobs, l.njobs, l.n, l.grid, s);
-    }
-    return hipErrorInvalidValue;
-}
-
 // Enqueue the launches of the given phase (-1: all), in order.
 hipError_t enqueue(const ih_batch_plan* p, int phase, hipStream_t s)
 {
-    for (const Launch& l : p->launches) {
-        if (phase >= 0 && phase_of(l) != phase) continue;
-        hipError_t e = run_launch(p, l, s);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return ih::enqueue_batch(p->image, p->d_image, phase, s);
 }
 
 void free_plan(ih_batch_plan* p)
@@ -92,27 +54,24 @@ void free_plan(ih_batch_plan* p)
     if (p->exec_all) (void)hipGraphExecDestroy(p->exec_all);
     for (auto& e : p->exec_phase)
         if (e) (void)hipGraphExecDestroy(e);
-    if (p->d_tables) (void)hipFree(p->d_tables);
+    if (p->d_image) (void)hipFree(p->d_image);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     delete p;
 }
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-// Lay out scratch and device tables, build the launch list.  Frames keep the
+// Lay out scratch, build the launch image and upload it.  Frames keep the
 // order given; tiles[k] is frame k's tile choice.
 ih_status build_plan(ih_batch_plan* p)
 {
     const size_t n = p->descs.size();
-    // scratch
     std::vector<size_t> off(n);
-    size_t words = 0;
     std::vector<ih::Geom> geoms(n);
+    size_t words = 0;
     for (size_t k = 0; k < n; ++k) {
         const ih_frame_desc& d = p->descs[k];
         geoms[k] = ih::make_geom(d.H, d.W, d.B, p->tiles[k]);
         off[k] = words;
-        words = align_up(words + ih::scratch_layout(geoms[k]).words, 64);
+        words += ih::frame_scratch_words(geoms[k]);
         p->entries += (int64_t)d.H * d.W * d.B;
     }
     hipError_t e = hipMalloc(&p->d_scratch, std::max<size_t>(words * 4, 256));
@@ -120,94 +79,21 @@ ih_status build_plan(ih_batch_plan* p)
         (void)hipGetLastError();
         return fail(IH_ERR_OOM, "batch scratch of %zu bytes: %s", words * 4, hipGetErrorString(e));
     }
-    p->frames.resize(n);
-    for (size_t k = 0; k < n; ++k)
-        p->frames[k] = ih::frame_args(p->descs[k].frame, p->descs[k].out,
-                                      static_cast<uint32_t*>(p->d_scratch) + off[k], geoms[k]);
-
-    // job tables
-    std::vector<std::vector<ih::Job>> tables;
-    std::vector<Launch> launches;
-    for (int tx : {32, 64}) {
-        std::vector<ih::Job> jobs;
-        int64_t begin = 0;
-        for (size_t k = 0; k < n; ++k) {
-            if (geoms[k].TX != tx) continue;
-            jobs.push_back(ih::Job{begin, (int32_t)k, 0, 0, 0});
-            begin += (int64_t)geoms[k].nTX * geoms[k].nTY;
-        }
-        if (jobs.empty()) continue;
-        Launch l;
-        l.kind = Launch::kAgg;
-        l.tx = tx;
-        l.n = begin;
-        l.njobs = (int32_t)jobs.size();
-        launches.push_back(l);
-        tables.push_back(std::move(jobs));
-    }
-    for (Launch::Kind kind : {Launch::kScanA, Launch::kScanB}) {
-        std::vector<ih::Job> jobs;
-        int64_t begin = 0;
-        for (size_t k = 0; k < n; ++k) {
-            const int64_t nb = kind == Launch::kScanA ? ih::scan_a_blocks(geoms[k]) : ih::scan_b_blocks(geoms[k]);
-            if (nb == 0) continue;
-            jobs.push_back(ih::Job{begin, (int32_t)k, 0, 0, 0});
-            begin += nb;
-        }
-        Launch l;
-        l.kind = kind;
-        l.n = begin;
-        l.njobs = (int32_t)jobs.size();
-        launches.push_back(l);
-        tables.push_back(std::move(jobs));
-    }
-    std::map<ih::TileVariant, std::vector<ih::Job>> byv;
-    std::map<ih::TileVariant, int64_t> items;
+    std::vector<ih::FrameArgs> frames(n);
+    std::vector<char> nt(n);
     for (size_t k = 0; k < n; ++k) {
-        const ih::Geom& g = geoms[k];
-        const int32_t n_int = ih::interior_groups(g, p->descs[k].frame, p->descs[k].out);
-        const int32_t parts[2][2] = {{0, n_int}, {n_int, g.nJG - n_int}};
-        for (int q = 0; q < 2; ++q) {
-            if (parts[q][1] <= 0) continue;
-            const ih::TileVariant v = ih::tile_variant(g, p->tiles[k].nontemporal, q == 1);
-            int64_t& b = items[v];
-            byv[v].push_back(ih::Job{b, (int32_t)k, parts[q][0], parts[q][1], 0});
-            b += (int64_t)g.nTY * parts[q][1];
-        }
+        frames[k] = ih::frame_args(p->descs[k].frame, p->descs[k].out,
+                                   static_cast<uint32_t*>(p->d_scratch) + off[k], geoms[k]);
+        nt[k] = p->tiles[k].nontemporal ? 1 : 0;
     }
-    for (auto& kv : byv) {
-        Launch l;
-        l.kind = Launch::kTile;
-        l.v = kv.first;
-        l.n = items[kv.first];
-        l.njobs = (int32_t)kv.second.size();
-        const int64_t want = (l.n + ih::kWavesPerBlock - 1) / ih::kWavesPerBlock;
-        l.grid = (int32_t)std::min<int64_t>(want, ih::tile_resident_blocks(kv.first));
-        launches.push_back(l);
-        tables.push_back(std::move(kv.second));
-    }
-
-    // one device allocation: FrameArgs table, then every job table
-    size_t bytes = align_up(n * sizeof(ih::FrameArgs), 256);
-    std::vector<size_t> toff(tables.size());
-    for (size_t t = 0; t < tables.size(); ++t) {
-        toff[t] = bytes;
-        bytes = align_up(bytes + tables[t].size() * sizeof(ih::Job), 256);
-    }
-    std::vector<unsigned char> host(bytes, 0);
-    std::memcpy(host.data(), p->frames.data(), n * sizeof(ih::FrameArgs));
-    for (size_t t = 0; t < tables.size(); ++t)
-        std::memcpy(host.data() + toff[t], tables[t].data(), tables[t].size() * sizeof(ih::Job));
-    e = hipMalloc(&p->d_tables, bytes);
+    ih::build_batch_image(frames, nt, &p->image);
+    e = hipMalloc(&p->d_image, p->image.bytes());
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(IH_ERR_OOM, "batch tables: %s", hipGetErrorString(e));
     }
-    e = hipMemcpy(p->d_tables, host.data(), bytes, hipMemcpyHostToDevice);
+    e = hipMemcpy(p->d_image, p->image.host.data(), p->image.bytes(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload batch tables");
-    for (size_t t = 0; t < tables.size(); ++t)
-        launches[t].jobs = reinterpret_cast<const ih::Job*>(static_cast<unsigned char*>(p->d_tables) + toff[t]);
-    p->launches = std::move(launches);
     return IH_OK;
 }
 
@@ -319,7 +205,7 @@ ih_status time_candidate(const std::vector<ih_frame_desc>& descs, const ih::Tile
     }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
-    if (p->d_scratch || p->d_tables) (void)hipDeviceSynchronize();
+    if (p->d_scratch || p->d_image) (void)hipDeviceSynchronize();
     free_plan(p);
     return st;
 }
@@ -440,10 +326,10 @@ ih_status ih_batch_plan_info(const ih_batch_plan* p, ih_batch_info* info)
     if (!p || !info) return fail(IH_ERR_INVALID_ARG, "plan and info must be non-null");
     info->frames = (int64_t)p->descs.size();
     info->entries = p->entries;
-    info->kernel_launches = (int32_t)p->launches.size();
+    info->kernel_launches = (int32_t)p->image.launches.size();
     info->graph = p->use_graph ? 1 : 0;
     int32_t tile_launches = 0;
-    for (const Launch& l : p->launches) tile_launches += l.kind == Launch::kTile;
+    for (const ih::BatchLaunch& l : p->image.launches) tile_launches += l.kind == ih::BatchLaunch::kTile;
     info->tile_launches = tile_launches;
     return IH_OK;
 }

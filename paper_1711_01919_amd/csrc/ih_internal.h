@@ -25,7 +25,7 @@ struct Geom {
 };
 
 // Scratch layout (uint32 words) for one frame:
-//   rowc   [H][nTX][B]    row counts per tile segment, scanned to left carries
+//   rowc   [H][nTX][B]    left carries: pixels of row y left of segment j, per bin
 //   colc   [nTY][W][B]    column counts per tile band, scanned to top carries
 //   corner [nTY][nTX][B]  per-tile totals, scanned to top-left corner counts
 struct ScratchLayout {
@@ -86,6 +86,10 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
 // ---- batched launches over a device FrameArgs table ----------------------
 hipError_t launch_agg_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
                             int64_t nblocks, hipStream_t stream);
+hipError_t launch_rowcarry_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                                 int64_t nblocks, size_t lds_bytes, hipStream_t stream);
+// LDS bytes the row-carry kernel needs for a frame.
+size_t rowcarry_lds(const Geom& g);
 hipError_t launch_scan_a_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
                                int64_t nblocks, hipStream_t stream);
 hipError_t launch_scan_b_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,

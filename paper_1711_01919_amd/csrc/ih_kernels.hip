@@ -74,12 +74,122 @@ __device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs,
 }
 
 // ---------------------------------------------------------------------------
-// Phase 1: per-tile bin counts
+// Phase 1a: left carries of every row (rowcarry)
 // ---------------------------------------------------------------------------
-constexpr int kAggRows = 32;     // rows whose segment counts are held in LDS at once
+// One wave per frame row.  For a chunk of up to kSegChunk tile segments the
+// wave bins the row's pixels into per-segment histograms in LDS (8-bit
+// counters: a segment holds at most TX <= 64 pixels), then each lane walks
+// the segments for its bins and stores the exclusive running count: rowc[y][j][b]
+// = pixels of row y left of segment j in bin b.
+constexpr int kSegChunk = 64;
+constexpr int kRowThreads = kWave;     // one row per workgroup
 
-// Two 16-bit counters per LDS word: row-segment counts are <= TX and column
-// counts are <= TY <= 65535, so a carry never crosses halves.
+__device__ __forceinline__ void lds_inc8(uint32_t* h, uint32_t e)
+{
+    atomicAdd(&h[e >> 2], 1u << ((e & 3u) << 3));
+}
+__device__ __forceinline__ uint32_t lds_get8(const uint32_t* h, uint32_t e)
+{
+    return (h[e >> 2] >> ((e & 3u) << 3)) & 0xFFu;
+}
+
+__device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uint32_t* lds)
+{
+    const Geom& g = f.g;
+    const int B = g.B, TX = g.TX, bpl = g.BPL;
+    const int lane = threadIdx.x;
+    uint32_t run[4] = {0u, 0u, 0u, 0u};
+    const IH_GLOBAL uint8_t* prow = gmem(f.frame) + y * g.W;
+    IH_GLOBAL uint32_t* out = gmem(f.rowc) + y * g.nTX * B;
+    // 16-byte chunks never straddle a segment (TX is a multiple of 16)
+    const bool vec = ((reinterpret_cast<uintptr_t>(prow) & 15) == 0);
+    for (int j0 = 0; j0 < g.nTX; j0 += kSegChunk) {
+        const int ns = min(kSegChunk, g.nTX - j0);
+        for (int w = lane; w < (ns * B + 3) / 4; w += kRowThreads) lds[w] = 0u;
+        __syncthreads();
+        const int x0 = j0 * TX;
+        const int npx = min(ns * TX, g.W - x0);
+        const int nchunks = (npx + 15) / 16;
+        for (int c0 = 0; c0 < nchunks; c0 += 4 * kRowThreads) {
+            // up to four 16-byte chunks per lane in flight before any counting
+            u32x4 w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * kRowThreads + lane;
+                const int p = c * 16;
+                if (c < nchunks && vec && p + 16 <= npx) {
+                    w[u] = *reinterpret_cast<const IH_GLOBAL u32x4*>(prow + x0 + p);
+                } else {
+                    uint32_t b4[4] = {0u, 0u, 0u, 0u};
+                    for (int k = 0; c < nchunks && k < 16 && p + k < npx; ++k)
+                        b4[k / 4] |= (uint32_t)prow[x0 + p + k] << (8 * (k % 4));
+                    w[u] = u32x4{b4[0], b4[1], b4[2], b4[3]};
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * kRowThreads + lane;
+                if (c >= nchunks) continue;
+                const int p = c * 16;
+                const uint32_t seg = (uint32_t)((p / TX) * B);
+                const uint32_t words[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    if (p + k < npx) {
+                        const uint32_t v = (words[k / 4] >> (8 * (k % 4))) & 0xFFu;
+                        lds_inc8(lds, seg + ((v * (uint32_t)B) >> 8));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int s = 0; s < ns; ++s) {
+            IH_GLOBAL uint32_t* o = out + (size_t)(j0 + s) * B;
+            for (int t = 0; t < bpl; ++t) {
+                const int b = lane * bpl + t;
+                if (b < B) {
+                    o[b] = run[t];
+                    run[t] += lds_get8(lds, (uint32_t)(s * B + b));
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// LDS bytes a row-carry workgroup needs for a frame: 8-bit counters for the
+// segments of one chunk.
+__host__ __device__ inline size_t rowcarry_lds_bytes(const Geom& g)
+{
+    const int ns = g.nTX < kSegChunk ? g.nTX : kSegChunk;
+    return ((size_t)ns * g.B + 3) / 4 * 4;
+}
+
+__global__ __launch_bounds__(kRowThreads)
+void rowcarry_kernel(FrameArgs f)
+{
+    extern __shared__ uint32_t lds[];
+    rowcarry_body(f, blockIdx.x, lds);
+}
+
+__global__ __launch_bounds__(kRowThreads)
+void rowcarry_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
+{
+    extern __shared__ uint32_t lds[];
+    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
+    const FrameArgs f = cload(frames, jb.frame);
+    rowcarry_body(f, (int64_t)blockIdx.x - jb.begin, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Phase 1b: per-tile column counts (agg)
+// ---------------------------------------------------------------------------
+// One 256-thread block per TY x TX tile: per-column bin counts of the tile
+// (16-bit LDS counters, <= TY pixels each), written to colc[i][x][b], and the
+// tile's total per bin, written to corner[i][j][b].
+
+// Two 16-bit counters per LDS word: column counts are <= TY <= 65535, so a
+// carry never crosses halves.
 __device__ __forceinline__ void lds_inc16(uint32_t* h, uint32_t e)
 {
     atomicAdd(&h[e >> 1], 1u << ((e & 1u) << 4));
@@ -90,8 +200,7 @@ __device__ __forceinline__ uint32_t lds_get16(const uint32_t* h, uint32_t e)
 }
 
 template <int TX>
-__device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile,
-                                         uint32_t* rowh, uint32_t* colh)
+__device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint32_t* colh)
 {
     constexpr int kRowsPerPass = kAggThreads / TX;
     const Geom& g = f.g;
@@ -105,28 +214,24 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile,
     const int tr = tid / TX, tx = tid % TX;
 
     for (int e = tid; e < (TX * B + 1) / 2; e += kAggThreads) colh[e] = 0;
-
-    for (int yc = 0; yc < th; yc += kAggRows) {
-        const int rows = min(kAggRows, th - yc);
-        for (int e = tid; e < (rows * B + 1) / 2; e += kAggThreads) rowh[e] = 0;
-        __syncthreads();                  // also orders the colh clearing before the first chunk
-        if (tx < tw) {
-            const IH_GLOBAL uint8_t* p = gmem(f.frame) + (size_t)(y0 + yc) * g.W + x0 + tx;
-            for (int r = tr; r < rows; r += kRowsPerPass) {
-                const uint32_t v = p[(size_t)r * g.W];
-                const uint32_t q = (v * (uint32_t)B) >> 8;
-                lds_inc16(rowh, (uint32_t)(r * B) + q);
-                lds_inc16(colh, (uint32_t)(tx * B) + q);
+    __syncthreads();
+    if (tx < tw) {
+        const IH_GLOBAL uint8_t* p = gmem(f.frame) + (size_t)y0 * g.W + x0 + tx;
+        constexpr int U = 8;                       // rows whose pixels are in flight together
+        for (int r0 = tr; r0 < th; r0 += U * kRowsPerPass) {
+            uint32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = r0 + u * kRowsPerPass;
+                v[u] = r < th ? (uint32_t)p[(size_t)r * g.W] : 0u;
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (r0 + u * kRowsPerPass < th)
+                    lds_inc16(colh, (uint32_t)(tx * B) + ((v[u] * (uint32_t)B) >> 8));
         }
-        __syncthreads();
-        for (int e = tid; e < rows * B; e += kAggThreads) {
-            const int r = e / B;
-            const int b = e - r * B;
-            gmem(f.rowc)[((size_t)(y0 + yc + r) * g.nTX + j) * B + b] = lds_get16(rowh, (uint32_t)e);
-        }
-        __syncthreads();
     }
+    __syncthreads();
     for (int e = tid; e < tw * B; e += kAggThreads)
         gmem(f.colc)[((size_t)i * g.W + x0) * B + e] = lds_get16(colh, (uint32_t)e);
     for (int b = tid; b < B; b += kAggThreads) {
@@ -140,20 +245,18 @@ template <int TX>
 __global__ __launch_bounds__(kAggThreads)
 void agg_kernel(FrameArgs f)
 {
-    __shared__ uint32_t rowh[kAggRows * 256 / 2];
     __shared__ uint32_t colh[TX * 256 / 2];
-    agg_body<TX>(f, blockIdx.x, rowh, colh);
+    agg_body<TX>(f, blockIdx.x, colh);
 }
 
 template <int TX>
 __global__ __launch_bounds__(kAggThreads)
 void agg_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
-    __shared__ uint32_t rowh[kAggRows * 256 / 2];
     __shared__ uint32_t colh[TX * 256 / 2];
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
-    agg_body<TX>(f, (int64_t)blockIdx.x - jb.begin, rowh, colh);
+    agg_body<TX>(f, (int64_t)blockIdx.x - jb.begin, colh);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,17 +283,14 @@ __device__ __forceinline__ void scan_seq(IH_GLOBAL uint32_t* p, int64_t stride, 
     }
 }
 
-// Row segments across tile columns, column counts across tile bands, tile
-// totals across bands -- independent sequences, one thread each.
+// Column counts across tile bands and tile totals across bands --
+// independent sequences, one thread each.
 __device__ __forceinline__ void scan_a_body(const FrameArgs& f, int64_t t)
 {
     const Geom& g = f.g;
     const int64_t B = g.B;
-    const int64_t nrow = (int64_t)g.H * B, ncol = (int64_t)g.W * B, ntot = (int64_t)g.nTX * B;
-    if (t < nrow) {
-        const int64_t y = t / B, b = t - y * B;
-        scan_seq(gmem(f.rowc) + y * g.nTX * B + b, B, g.nTX);
-    } else if ((t -= nrow) < ncol) {
+    const int64_t ncol = (int64_t)g.W * B, ntot = (int64_t)g.nTX * B;
+    if (t < ncol) {
         scan_seq(gmem(f.colc) + t, (int64_t)g.W * B, g.nTY);
     } else if ((t -= ncol) < ntot) {
         scan_seq(gmem(f.corner) + t, (int64_t)g.nTX * B, g.nTY);
@@ -610,9 +710,11 @@ static TileFns tile_fns(const TileVariant& v)
     return v.guard ? pick_v<false, true>(v) : pick_v<false, false>(v);
 }
 
+size_t rowcarry_lds(const Geom& g) { return rowcarry_lds_bytes(g); }
+
 int64_t scan_a_blocks(const Geom& g)
 {
-    const int64_t n = (int64_t)g.H * g.B + (int64_t)g.W * g.B + (int64_t)g.nTX * g.B;
+    const int64_t n = (int64_t)g.W * g.B + (int64_t)g.nTX * g.B;
     return (n + kScanThreads - 1) / kScanThreads;
 }
 
@@ -626,6 +728,8 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
     const Geom& g = f.g;
     switch (ph) {
     case Phase::kAgg: {
+        hipLaunchKernelGGL(rowcarry_kernel, dim3((unsigned)g.H), dim3(kRowThreads),
+                           (unsigned)rowcarry_lds_bytes(g), stream, f);
         const unsigned ntiles = (unsigned)g.nTX * (unsigned)g.nTY;
         if (g.TX == 32)
             hipLaunchKernelGGL(agg_kernel<32>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
@@ -668,6 +772,15 @@ hipError_t launch_agg_batch(int TX, const FrameArgs* frames, const Job* jobs, in
     else
         hipLaunchKernelGGL(agg_batch_kernel<64>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,
                            frames, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowcarry_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                                 int64_t nblocks, size_t lds_bytes, hipStream_t stream)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rowcarry_batch_kernel, dim3((unsigned)nblocks), dim3(kRowThreads), (unsigned)lds_bytes,
+                       stream, frames, jobs, njobs);
     return hipGetLastError();
 }
 

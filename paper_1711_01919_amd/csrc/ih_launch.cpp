@@ -1,0 +1,157 @@
+// Batched launch images (see ih_launch.h).
+#include "ih_launch.h"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+namespace ih {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t frame_scratch_words(const Geom& g) { return align_up(scratch_layout(g).words, 64); }
+
+int phase_of(const BatchLaunch& l)
+{
+    switch (l.kind) {
+    case BatchLaunch::kRowCarry:
+    case BatchLaunch::kAgg: return 0;
+    case BatchLaunch::kScanA:
+    case BatchLaunch::kScanB: return 1;
+    default: return 2;
+    }
+}
+
+// Resident workgroups per tile-kernel variant, asked of the runtime once.
+static int32_t resident_blocks_cached(const TileVariant& v)
+{
+    static std::mutex mu;
+    static std::map<TileVariant, int32_t>* cache = new std::map<TileVariant, int32_t>;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache->find(v);
+    if (it != cache->end()) return it->second;
+    const int32_t r = tile_resident_blocks(v);
+    (*cache)[v] = r;
+    return r;
+}
+
+void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<char>& nontemporal,
+                       BatchImage* img)
+{
+    const size_t n = frames.size();
+    std::vector<std::vector<Job>> tables;
+    std::vector<BatchLaunch> launches;
+
+    {
+        std::vector<Job> jobs;
+        int64_t begin = 0;
+        size_t lds = 0;
+        for (size_t k = 0; k < n; ++k) {
+            jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
+            begin += frames[k].g.H;                       // one workgroup per row
+            lds = std::max(lds, rowcarry_lds(frames[k].g));
+        }
+        BatchLaunch l;
+        l.kind = BatchLaunch::kRowCarry;
+        l.lds = lds;
+        l.n = begin;
+        l.njobs = (int32_t)jobs.size();
+        launches.push_back(l);
+        tables.push_back(std::move(jobs));
+    }
+
+    for (int tx : {32, 64}) {
+        std::vector<Job> jobs;
+        int64_t begin = 0;
+        for (size_t k = 0; k < n; ++k) {
+            const Geom& g = frames[k].g;
+            if (g.TX != tx) continue;
+            jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
+            begin += (int64_t)g.nTX * g.nTY;
+        }
+        if (jobs.empty()) continue;
+        BatchLaunch l;
+        l.kind = BatchLaunch::kAgg;
+        l.tx = tx;
+        l.n = begin;
+        l.njobs = (int32_t)jobs.size();
+        launches.push_back(l);
+        tables.push_back(std::move(jobs));
+    }
+    for (BatchLaunch::Kind kind : {BatchLaunch::kScanA, BatchLaunch::kScanB}) {
+        std::vector<Job> jobs;
+        int64_t begin = 0;
+        for (size_t k = 0; k < n; ++k) {
+            const int64_t nb = kind == BatchLaunch::kScanA ? scan_a_blocks(frames[k].g) : scan_b_blocks(frames[k].g);
+            if (nb == 0) continue;
+            jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
+            begin += nb;
+        }
+        if (jobs.empty()) continue;
+        BatchLaunch l;
+        l.kind = kind;
+        l.n = begin;
+        l.njobs = (int32_t)jobs.size();
+        launches.push_back(l);
+        tables.push_back(std::move(jobs));
+    }
+    std::map<TileVariant, std::vector<Job>> byv;
+    std::map<TileVariant, int64_t> items;
+    for (size_t k = 0; k < n; ++k) {
+        const Geom& g = frames[k].g;
+        const int32_t n_int = interior_groups(g, frames[k].frame, frames[k].out);
+        const int32_t parts[2][2] = {{0, n_int}, {n_int, g.nJG - n_int}};
+        for (int q = 0; q < 2; ++q) {
+            if (parts[q][1] <= 0) continue;
+            const TileVariant v = tile_variant(g, nontemporal[k] != 0, q == 1);
+            int64_t& b = items[v];
+            byv[v].push_back(Job{b, (int32_t)k, parts[q][0], parts[q][1], 0});
+            b += (int64_t)g.nTY * parts[q][1];
+        }
+    }
+    for (auto& kv : byv) {
+        BatchLaunch l;
+        l.kind = BatchLaunch::kTile;
+        l.v = kv.first;
+        l.n = items[kv.first];
+        l.njobs = (int32_t)kv.second.size();
+        const int64_t want = (l.n + kWavesPerBlock - 1) / kWavesPerBlock;
+        l.grid = (int32_t)std::min<int64_t>(want, resident_blocks_cached(kv.first));
+        launches.push_back(l);
+        tables.push_back(std::move(kv.second));
+    }
+
+    size_t bytes = align_up(n * sizeof(FrameArgs), 256);
+    for (size_t t = 0; t < tables.size(); ++t) {
+        launches[t].jobs_off = bytes;
+        bytes = align_up(bytes + tables[t].size() * sizeof(Job), 256);
+    }
+    img->host.assign(bytes, 0);
+    std::memcpy(img->host.data(), frames.data(), n * sizeof(FrameArgs));
+    for (size_t t = 0; t < tables.size(); ++t)
+        std::memcpy(img->host.data() + launches[t].jobs_off, tables[t].data(), tables[t].size() * sizeof(Job));
+    img->launches = std::move(launches);
+}
+
+hipError_t enqueue_batch(const BatchImage& img, const void* dev_image, int phase, hipStream_t s)
+{
+    const unsigned char* base = static_cast<const unsigned char*>(dev_image);
+    const FrameArgs* fr = reinterpret_cast<const FrameArgs*>(base);
+    for (const BatchLaunch& l : img.launches) {
+        if (phase >= 0 && phase_of(l) != phase) continue;
+        const Job* jobs = reinterpret_cast<const Job*>(base + l.jobs_off);
+        hipError_t e = hipSuccess;
+        switch (l.kind) {
+        case BatchLaunch::kRowCarry: e = launch_rowcarry_batch(fr, jobs, l.njobs, l.n, l.lds, s); break;
+        case BatchLaunch::kAgg: e = launch_agg_batch(l.tx, fr, jobs, l.njobs, l.n, s); break;
+        case BatchLaunch::kScanA: e = launch_scan_a_batch(fr, jobs, l.njobs, l.n, s); break;
+        case BatchLaunch::kScanB: e = launch_scan_b_batch(fr, jobs, l.njobs, l.n, s); break;
+        case BatchLaunch::kTile: e = launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid, s); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace ih

@@ -1,0 +1,46 @@
+// Batched launch images: the device tables (frame descriptors + job tables)
+// and the launch list that run the three phases for many frames at once.
+// Used by batch plans (fixed buffers, replayed from a hipGraph) and by the
+// serving loop (a fresh image per dispatch).
+#pragma once
+
+#include "ih_internal.h"
+
+#include <vector>
+
+namespace ih {
+
+struct BatchLaunch {
+    enum Kind { kRowCarry, kAgg, kScanA, kScanB, kTile } kind = kAgg;
+    int tx = 64;               // kAgg: tile width of the frames it covers
+    TileVariant v{};           // kTile: compiled kernel variant
+    size_t jobs_off = 0;       // byte offset of this launch's job table in the image
+    int32_t njobs = 0;
+    int64_t n = 0;             // blocks (kAgg, kScan*) or work items (kTile)
+    int32_t grid = 0;          // kTile: persistent workgroups
+    size_t lds = 0;            // kRowCarry: dynamic LDS bytes
+};
+
+struct BatchImage {
+    std::vector<unsigned char> host;      // FrameArgs[n] at offset 0, then job tables
+    std::vector<BatchLaunch> launches;
+    size_t bytes() const { return host.size(); }
+};
+
+size_t align_up(size_t v, size_t a);
+
+// Scratch words a frame needs for the given tile.
+size_t frame_scratch_words(const Geom& g);
+
+// Fill img from fully set-up frames (device pointers, scratch included).
+// nontemporal[k] picks the store flavour of frame k.
+void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<char>& nontemporal,
+                       BatchImage* img);
+
+// Enqueue the image's launches of one phase (-1: all phases) on s.  dev_image
+// is a device copy of img.host that stays valid until the work has run.
+hipError_t enqueue_batch(const BatchImage& img, const void* dev_image, int phase, hipStream_t s);
+
+int phase_of(const BatchLaunch& l);
+
+}  // namespace ih
