@@ -12,8 +12,9 @@ resident in HBM before the timed region starts.
 
 Prints ONE JSON line: throughput (entries/s) of the batched step; the same
 frames through 64 plain per-frame ih_compute calls for comparison; the
-roofline of the dominant kernel (the tile pass, HBM-bound); a write-stream
-ceiling measured with a plain fill; the serving loop's p50/p99 latency and
+roofline of the dominant kernel (the tile pass, HBM-bound); the 640x480
+B=32 frame and the 8192x8192 B=128 frame through ih_compute with their
+region queries; the serving loop's p50/p99 latency and
 throughput on a replayed 16-stream trace next to the plain per-frame path;
 and the single-threaded CPU oracle timed on a bounded sample of the batched
 workload.
@@ -85,21 +86,46 @@ def timed(torch, stream, fn, steps):
     return ev0.elapsed_time(ev1)
 
 
-def write_ceiling(torch, stream, gib: int = 16, reps: int = 3) -> float:
-    """GB/s of a plain streaming write of distinct values (torch's own arange
-    kernel, 2 GiB per launch) over a buffer far larger than the 256 MB
-    last-level cache: the write-stream ceiling of the chip for data that does
-    not repeat."""
-    chunk = (2 << 30) // 4
-    bufs = [torch.empty(chunk, dtype=torch.int32, device="cuda") for _ in range(gib // 2)]
-
-    def fill():
-        for b in bufs:
-            torch.arange(chunk, out=b)
-    fill()
-    ms = timed(torch, stream, fill, reps)
-    del bufs
-    return chunk * 4 * (gib // 2) * reps / (ms / 1e3) / 1e9
+def plain_and_query_legs(torch, ihb, synth, stream) -> dict:
+    """The 640x480 B=32 frame through ih_compute (per-call time over many
+    calls) with its 1000 rectangles, and 1e6 rectangles on the 8192x8192
+    B=128 mixture frame; queries read rectangles already on the device.
+    Algorithmic query bytes: 4 corners x B x 4 read + B x 4 written = 20*B
+    per rectangle."""
+    out = {}
+    I, B, rects = synth.plain_frame()
+    H, W = I.shape
+    f = torch.from_numpy(I).cuda()
+    ih = torch.empty((H, W, B), dtype=torch.uint32, device="cuda")
+    rd = torch.from_numpy(rects).cuda()
+    hs = torch.empty((len(rects), B), dtype=torch.uint32, device="cuda")
+    for _ in range(20):
+        ihb.compute(f, B, out=ih, stream=stream)
+    reps = 400
+    ms = timed(torch, stream, lambda: ihb.compute(f, B, out=ih, stream=stream), reps) / reps
+    qms = timed(torch, stream, lambda: ihb.query_device(ih, rd, out=hs, stream=stream), reps) / reps
+    out["plain_frame_640x480_B32"] = {"ms_per_frame": ms, "entries_per_s": H * W * B / (ms / 1e3),
+                                      "query_1000_rects_ms": qms}
+    del f, ih, rd, hs
+    I, B, rects = synth.mixture_frame()
+    H, W = I.shape
+    f = torch.from_numpy(I).cuda()
+    ih = torch.empty((H, W, B), dtype=torch.uint32, device="cuda")
+    ihb.compute(f, B, out=ih, stream=stream)
+    ms = timed(torch, stream, lambda: ihb.compute(f, B, out=ih, stream=stream), 3) / 3
+    rd = torch.from_numpy(rects).cuda()
+    hs = torch.empty((len(rects), B), dtype=torch.uint32, device="cuda")
+    ihb.query_device(ih, rd, out=hs, stream=stream)
+    qms = timed(torch, stream, lambda: ihb.query_device(ih, rd, out=hs, stream=stream), 10) / 10
+    n = len(rects)
+    out["mixture_frame_8192x8192_B128"] = {
+        "ms_per_frame": ms, "entries_per_s": H * W * B / (ms / 1e3),
+        "hbm_frac": (H * W + 4 * H * W * B) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "query_1e6_rects_ms": qms, "rects_per_s": n / (qms / 1e3),
+        "query_gbs": 20 * B * n / (qms / 1e3) / 1e9}
+    del f, ih, rd, hs
+    torch.cuda.empty_cache()
+    return out
 
 
 def percentiles(xs):
@@ -254,12 +280,12 @@ def main():
     ms_plain = timed(torch, stream, plain_step, plain_steps) / plain_steps
     log(f"[bench] plain loop: {ms_plain:.3f} ms/step")
 
-    ceiling = write_ceiling(torch, stream)
-    log(f"[bench] write-stream ceiling (fill): {ceiling:.0f} GB/s")
 
     plan.close()
     del outs, plan
     torch.cuda.empty_cache()
+    legs = plain_and_query_legs(torch, ihb, synth, stream)
+    log(f"[bench] plain/query legs: {legs}")
     served = None
     if args.serve_seconds > 0:
         served = serving_leg(torch, ihb, synth, args.serve_seconds)
@@ -277,11 +303,11 @@ def main():
         "plain_loop": {"value": entries_step / (ms_plain / 1e3), "ms_per_step": ms_plain,
                        "speedup_batched": ms_plain / ms_step},
         "phase_ms_per_step": {k: ph[k] / args.steps for k in ("agg_ms", "scan_ms", "tile_ms")},
-        "write_ceiling_gbs": ceiling,
         "roofline": {"bound": "hbm", "kernel": "tile_batch_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "alg_bytes_per_launch": alg_bytes_launch},
     }
+    rec.update(legs)
     if served is not None:
         rec["serving"] = served
     if not args.no_cpu_baseline:

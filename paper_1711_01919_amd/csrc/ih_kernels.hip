@@ -60,6 +60,14 @@ __device__ __forceinline__ T cload(const T* table, int64_t idx)
     return v;
 }
 
+// Index of the calling wave within its workgroup.  The value is the same on
+// every lane of a wave, and saying so keeps what is derived from it (work
+// item, frame, loop bounds) in scalar registers.
+__device__ __forceinline__ int wave_in_block()
+{
+    return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+}
+
 // Largest job whose `begin` is <= idx (jobs sorted by begin, jobs[0].begin == 0).
 // idx is uniform across the caller's wave, so the loads stay scalar.
 __device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs, int64_t idx)
@@ -500,14 +508,6 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
     }
 }
 
-// Index of the calling wave within its workgroup.  The value is the same on
-// every lane of a wave, and saying so keeps what is derived from it (work
-// item, frame, loop bounds) in scalar registers.
-__device__ __forceinline__ int wave_in_block()
-{
-    return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-}
-
 template <int BPL, int TX, int BC, bool NT, bool GUARD>
 __global__ __launch_bounds__(kWave * kWavesPerBlock)
 void tile_kernel(FrameArgs f, int32_t jg_begin, int32_t jg_count)
@@ -538,36 +538,59 @@ void tile_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Region query (Sec. 2.1, Eq. 2): one thread per (rectangle, bin)
+// Region query (Sec. 2.1, Eq. 2)
 // ---------------------------------------------------------------------------
+// Lanes run over bins.  For B >= 64 a wave answers one rectangle (its corners
+// are wave-uniform and come in through scalar loads) in chunks of 64 bins;
+// for B < 64 a wave answers floor(64 / B) rectangles side by side.  Each
+// lane gathers its bin from the four corners -- B contiguous uint32 per
+// corner across the lanes -- and writes h(R, b).
 constexpr int kQueryThreads = 256;
 
-__global__ __launch_bounds__(kQueryThreads)
-void query_kernel(const uint32_t* __restrict__ ih, int32_t H, int32_t W, int32_t B,
-                  const int32_t* __restrict__ rects, int64_t n,
-                  uint32_t* __restrict__ hists, uint32_t* __restrict__ bad)
+__device__ __forceinline__ uint32_t four_corners(const IH_GLOBAL uint32_t* ih, int32_t W, int32_t B,
+                                                 int32_t x0, int32_t y0, int32_t x1, int32_t y1, int b)
 {
-    const int64_t t = (int64_t)blockIdx.x * kQueryThreads + threadIdx.x;
-    if (t >= n * B) return;
-    const int64_t r = t / B;
-    const int b = (int)(t - r * B);
-    const int32_t x0 = rects[4 * r + 0], y0 = rects[4 * r + 1];
-    const int32_t x1 = rects[4 * r + 2], y1 = rects[4 * r + 3];
-    const bool ok = x0 >= 0 && x0 <= x1 && x1 < W && y0 >= 0 && y0 <= y1 && y1 < H;
-    uint32_t h = 0;
-    if (ok) {
-        const size_t rowA = (size_t)y1 * W;               // row y1
-        h = ih[(rowA + x1) * B + b];
-        if (x0 > 0) h -= ih[(rowA + x0 - 1) * B + b];
-        if (y0 > 0) {
-            const size_t rowB = (size_t)(y0 - 1) * W;      // row y0-1
-            h -= ih[(rowB + x1) * B + b];
-            if (x0 > 0) h += ih[(rowB + x0 - 1) * B + b];
-        }
-    } else if (b == 0 && bad) {
-        atomicAdd(bad, 1u);
+    const size_t rowA = (size_t)y1 * W;                   // row y1
+    uint32_t h = ih[(rowA + x1) * B + b];
+    if (x0 > 0) h -= ih[(rowA + x0 - 1) * B + b];
+    if (y0 > 0) {
+        const size_t rowB = (size_t)(y0 - 1) * W;          // row y0-1
+        h -= ih[(rowB + x1) * B + b];
+        if (x0 > 0) h += ih[(rowB + x0 - 1) * B + b];
     }
-    hists[t] = h;
+    return h;
+}
+
+__global__ __launch_bounds__(kQueryThreads)
+void query_kernel(const uint32_t* __restrict__ ih_, int32_t H, int32_t W, int32_t B,
+                  const int32_t* __restrict__ rects, int64_t n,
+                  uint32_t* __restrict__ hists_, uint32_t* __restrict__ bad)
+{
+    const IH_GLOBAL uint32_t* ih = gmem(ih_);
+    IH_GLOBAL uint32_t* hists = gmem(hists_);
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = (int64_t)blockIdx.x * (kQueryThreads / kWave) + wave_in_block();
+    if (B >= kWave) {
+        const int64_t r = wave;
+        if (r >= n) return;
+        const IH_CONST int32_t* rc = cmem(rects) + 4 * r;     // one rectangle per wave: scalar loads
+        const int32_t x0 = rc[0], y0 = rc[1], x1 = rc[2], y1 = rc[3];
+        const bool ok = x0 >= 0 && x0 <= x1 && x1 < W && y0 >= 0 && y0 <= y1 && y1 < H;
+        if (!ok && lane == 0 && bad) atomicAdd(bad, 1u);
+        for (int b = lane; b < B; b += kWave)
+            hists[r * B + b] = ok ? four_corners(ih, W, B, x0, y0, x1, y1, b) : 0u;
+    } else {
+        const int per = kWave / B;                            // rectangles per wave
+        const int sub = lane / B;
+        const int b = lane - sub * B;
+        const int64_t r = wave * per + sub;
+        if (sub >= per || r >= n) return;
+        const IH_GLOBAL int32_t* rc = gmem(rects) + 4 * r;
+        const int32_t x0 = rc[0], y0 = rc[1], x1 = rc[2], y1 = rc[3];
+        const bool ok = x0 >= 0 && x0 <= x1 && x1 < W && y0 >= 0 && y0 <= y1 && y1 < H;
+        if (!ok && b == 0 && bad) atomicAdd(bad, 1u);
+        hists[r * B + b] = ok ? four_corners(ih, W, B, x0, y0, x1, y1, b) : 0u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -830,9 +853,11 @@ hipError_t launch_query(const uint32_t* ih, int32_t H, int32_t W, int32_t B,
                         uint32_t* bad_count, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
-    const int64_t nt = n * B;
-    hipLaunchKernelGGL(query_kernel, dim3((unsigned)((nt + kQueryThreads - 1) / kQueryThreads)),
-                       dim3(kQueryThreads), 0, stream, ih, H, W, B, rects, n, hists, bad_count);
+    const int64_t per = B >= kWave ? 1 : kWave / B;           // rectangles per wave
+    const int64_t waves = (n + per - 1) / per;
+    const int64_t blocks = (waves + kQueryThreads / kWave - 1) / (kQueryThreads / kWave);
+    hipLaunchKernelGGL(query_kernel, dim3((unsigned)blocks), dim3(kQueryThreads), 0, stream,
+                       ih, H, W, B, rects, n, hists, bad_count);
     return hipGetLastError();
 }
 
