@@ -39,7 +39,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the 64-frame plan (default: the batch heuristic tile)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 256-frame uneven batch leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -126,6 +128,39 @@ def plain_and_query_legs(torch, ihb, synth, stream) -> dict:
     del f, ih, rd, hs
     torch.cuda.empty_cache()
     return out
+
+
+def uneven_leg(torch, ihb, synth, stream) -> dict:
+    """256 frames of five resolutions and four bin counts (seed 3) through one
+    autotuned batched plan (one graph launch), against 256 plain ih_compute
+    calls on the same buffers."""
+    ub = synth.uneven_batch()
+    fr = [torch.from_numpy(f).cuda() for f in ub.frames]
+    outs = [torch.empty((f.shape[0], f.shape[1], b), dtype=torch.uint32, device="cuda")
+            for f, b in zip(ub.frames, ub.bins)]
+    t0 = time.time()
+    plan = ihb.BatchPlan(fr, outs, ub.bins, autotune=True, stream=stream)
+    tune_s = time.time() - t0
+    plan.launch(stream)
+    ms = timed(torch, stream, lambda: plan.launch(stream), 3) / 3
+    tiles = sorted({(f.shape[0], f.shape[1], b) + plan.frame_tile(k)
+                    for k, (f, b) in enumerate(zip(ub.frames, ub.bins))})
+
+    def plain():
+        for k, b in enumerate(ub.bins):
+            ihb.compute(fr[k], b, out=outs[k], stream=stream)
+    plain()
+    ms_plain = timed(torch, stream, plain, 3) / 3
+    info = plan.info()
+    plan.close()
+    del plan, plain, fr, outs
+    torch.cuda.empty_cache()
+    ent = ub.entries
+    return {"frames": len(ub.frames), "entries": ent, "ms_per_launch": ms, "entries_per_s": ent / (ms / 1e3),
+            "hbm_frac": (4 * ent + sum(f.size for f in ub.frames)) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "plain_loop_ms": ms_plain, "speedup_batched": ms_plain / ms, "autotune_s": tune_s,
+            "kernel_launches": info["kernel_launches"],
+            "tiles": [f"{h}x{w} B{b}: {tx}x{ty}{' nt' if nt else ''}" for h, w, b, tx, ty, nt in tiles]}
 
 
 def percentiles(xs):
@@ -239,7 +274,7 @@ def main():
 
     t0 = time.time()
     plan = ihb.BatchPlan([d_frames[k] for k in range(n)], outs, [B] * n,
-                         autotune=not args.no_autotune, stream=stream)
+                         autotune=args.autotune, stream=stream)
     tile = plan.frame_tile(0)
     info = plan.info()
     log(f"[bench] plan ready in {time.time() - t0:.1f}s: tile {tile}, {info}")
@@ -286,7 +321,11 @@ def main():
     torch.cuda.empty_cache()
     legs = plain_and_query_legs(torch, ihb, synth, stream)
     log(f"[bench] plain/query legs: {legs}")
+    if not args.no_uneven:
+        legs["uneven_batch_256"] = uneven_leg(torch, ihb, synth, stream)
+        log(f"[bench] uneven batch: {legs['uneven_batch_256']}")
     served = None
+    torch.cuda.empty_cache()
     if args.serve_seconds > 0:
         served = serving_leg(torch, ihb, synth, args.serve_seconds)
         log(f"[bench] serving: {served}")

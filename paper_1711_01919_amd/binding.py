@@ -233,6 +233,7 @@ class BatchPlan:
         if self._h:
             _check(lib.ih_batch_plan_destroy(self._h), "ih_batch_plan_destroy")
             self._h = None
+            self._keep = None
 
     def __del__(self):
         try:

@@ -121,8 +121,16 @@ ih_status capture(ih_batch_plan* p, int phase, hipGraphExec_t* out)
 // ---------------------------------------------------------------------------
 struct TuneKey {
     int32_t H, W, B;
-    bool operator<(const TuneKey& o) const { return std::tie(H, W, B) < std::tie(o.H, o.W, o.B); }
+    int32_t nb;          // frames of the class, as floor(log2(n)): tiles depend on the parallelism
+    bool operator<(const TuneKey& o) const { return std::tie(H, W, B, nb) < std::tie(o.H, o.W, o.B, o.nb); }
 };
+
+int32_t log2_floor(size_t n)
+{
+    int32_t r = 0;
+    while (n > 1) { n >>= 1; ++r; }
+    return r;
+}
 
 struct TuneCache {
     std::mutex mu;
@@ -137,7 +145,7 @@ TuneCache& tune_cache()
 
 const char* cache_path() { return std::getenv("IH_AUTOTUNE_CACHE"); }
 
-// The cache file holds one line per class: "gfx950 H W B TX TY NT".
+// The cache file holds one line per class: "gfx950 H W B NB TX TY NT".
 void load_cache(TuneCache& c)
 {
     if (c.loaded) return;
@@ -146,11 +154,11 @@ void load_cache(TuneCache& c)
     if (!path) return;
     std::ifstream in(path);
     std::string arch;
-    int H, W, B, TX, TY, NT;
-    while (in >> arch >> H >> W >> B >> TX >> TY >> NT) {
+    int H, W, B, NB, TX, TY, NT;
+    while (in >> arch >> H >> W >> B >> NB >> TX >> TY >> NT) {
         if (arch != "gfx950") continue;
         ih::TileChoice t{TX, TY, NT != 0};
-        if (ih::tile_supported(B, t)) c.best[TuneKey{H, W, B}] = t;
+        if (ih::tile_supported(B, t)) c.best[TuneKey{H, W, B, NB}] = t;
     }
 }
 
@@ -160,7 +168,7 @@ void save_cache(TuneCache& c)
     if (!path) return;
     std::ofstream out(path);
     for (auto& kv : c.best)
-        out << "gfx950 " << kv.first.H << ' ' << kv.first.W << ' ' << kv.first.B << ' ' << kv.second.TX
+        out << "gfx950 " << kv.first.H << ' ' << kv.first.W << ' ' << kv.first.B << ' ' << kv.first.nb << ' ' << kv.second.TX
             << ' ' << kv.second.TY << ' ' << (kv.second.nontemporal ? 1 : 0) << '\n';
 }
 
@@ -174,6 +182,24 @@ std::vector<ih::TileChoice> candidates(int32_t B)
                 if (ih::tile_supported(B, t)) c.push_back(t);
             }
     return c;
+}
+
+// Heuristic tile for frames of one bin count launched together: the widest
+// tile column of the bin class, and the tallest band (fewest carries) that
+// still leaves at least 8192 independent waves across all of the frames.
+ih::TileChoice batch_default_tile(const std::vector<ih_frame_desc>& descs, int32_t B)
+{
+    ih::TileChoice t = ih::default_tile(descs[0].H, descs[0].W, B);
+    for (int ty : {256, 128, 64, 32, 16}) {
+        int64_t waves = 0;
+        for (const ih_frame_desc& d : descs) {
+            const ih::Geom g = ih::make_geom(d.H, d.W, d.B, ih::TileChoice{t.TX, ty, false});
+            waves += (int64_t)g.nTY * g.nJG;
+        }
+        t.TY = ty;
+        if (waves >= 8192) break;
+    }
+    return t;
 }
 
 // Time one candidate on the frames of a class (all phases, no graph).
@@ -190,17 +216,18 @@ ih_status time_candidate(const std::vector<ih_frame_desc>& descs, const ih::Tile
         hipError_t e = hipEventCreate(&a);
         if (e == hipSuccess) e = hipEventCreate(&b);
         if (e == hipSuccess) e = enqueue(p, -1, s);                      // warm-up
-        float best = 1e30f;
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+        std::vector<float> runs;
+        for (int r = 0; r < 5 && e == hipSuccess; ++r) {
             e = hipEventRecord(a, s);
             if (e == hipSuccess) e = enqueue(p, -1, s);
             if (e == hipSuccess) e = hipEventRecord(b, s);
             if (e == hipSuccess) e = hipEventSynchronize(b);
             float m = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&m, a, b);
-            best = std::min(best, m);
+            runs.push_back(m);
         }
-        *ms = best;
+        std::sort(runs.begin(), runs.end());
+        *ms = runs.empty() ? 1e30f : runs[runs.size() / 2];
         if (e != hipSuccess) st = hip_fail(e, "autotune run");
     }
     if (a) (void)hipEventDestroy(a);
@@ -210,28 +237,35 @@ ih_status time_candidate(const std::vector<ih_frame_desc>& descs, const ih::Tile
     return st;
 }
 
+// The class's frames measured alone: the heuristic tile first, then every
+// candidate; a candidate replaces the incumbent only when its median time is
+// more than 2% lower, so timing noise does not flip the choice.
 ih_status autotune(ih_batch_plan* p, hipStream_t s)
 {
     std::map<TuneKey, std::vector<size_t>> classes;
     for (size_t k = 0; k < p->descs.size(); ++k)
-        classes[TuneKey{p->descs[k].H, p->descs[k].W, p->descs[k].B}].push_back(k);
+        classes[TuneKey{p->descs[k].H, p->descs[k].W, p->descs[k].B, 0}].push_back(k);
     TuneCache& c = tune_cache();
     std::lock_guard<std::mutex> lock(c.mu);
     load_cache(c);
     bool dirty = false;
     for (auto& kv : classes) {
-        auto hit = c.best.find(kv.first);
+        TuneKey key = kv.first;
+        key.nb = log2_floor(kv.second.size());
+        auto hit = c.best.find(key);
         if (hit == c.best.end()) {
             std::vector<ih_frame_desc> descs;
             for (size_t k : kv.second) descs.push_back(p->descs[k]);
-            ih::TileChoice best = ih::default_tile(kv.first.H, kv.first.W, kv.first.B);
+            ih::TileChoice best = batch_default_tile(descs, kv.first.B);
             float best_ms = 1e30f;
+            if (ih_status st = time_candidate(descs, best, s, &best_ms)) return st;
             for (const ih::TileChoice& t : candidates(kv.first.B)) {
+                if (t.TX == best.TX && t.TY == best.TY && t.nontemporal == best.nontemporal) continue;
                 float ms = 0.f;
                 if (ih_status st = time_candidate(descs, t, s, &ms)) return st;
-                if (ms < best_ms) { best_ms = ms; best = t; }
+                if (ms < 0.98f * best_ms) { best_ms = ms; best = t; }
             }
-            hit = c.best.emplace(kv.first, best).first;
+            hit = c.best.emplace(key, best).first;
             dirty = true;
         }
         for (size_t k : kv.second) p->tiles[k] = hit->second;
@@ -274,7 +308,11 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     } else if (o.autotune) {
         st = autotune(p, s);
     } else {
-        for (size_t k = 0; k < n; ++k) p->tiles[k] = ih::default_tile(frames[k].H, frames[k].W, frames[k].B);
+        std::map<int32_t, std::vector<ih_frame_desc>> by_b;
+        for (size_t k = 0; k < n; ++k) by_b[frames[k].B].push_back(frames[k]);
+        std::map<int32_t, ih::TileChoice> choice;
+        for (auto& kv : by_b) choice[kv.first] = batch_default_tile(kv.second, kv.first);
+        for (size_t k = 0; k < n; ++k) p->tiles[k] = choice[frames[k].B];
     }
     if (st == IH_OK && o.nontemporal >= 0)
         for (auto& t : p->tiles) t.nontemporal = o.nontemporal != 0;

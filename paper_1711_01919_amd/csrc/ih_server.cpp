@@ -24,6 +24,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <string>
 #include <vector>
 
 namespace {
@@ -194,6 +195,7 @@ struct Request {
     ih::Geom geom{};
     ih_timing t{0, 0, 0};
     ih_status status = IH_OK;
+    std::string detail;      // error text recorded on the scheduler thread
     bool done = false;
 };
 
@@ -417,6 +419,7 @@ bool reap(ih_server* s)
                 if (!keep) s->arena.release(r.ih_off, r.ih_bytes);
                 r.t.t_done_ns = t;
                 r.status = st;
+                if (st != IH_OK) r.detail = ih_last_error();
                 r.done = true;
                 s->admitted -= 1;
             }
@@ -437,6 +440,7 @@ void fail_pending(ih_server* s, ih_status st)
     const uint64_t t = now_ns();
     for (auto& rp : s->pending) {
         rp->status = st;
+        rp->detail = ih_last_error();
         rp->done = true;
         rp->t.t_done_ns = t;
     }
@@ -491,6 +495,7 @@ void scheduler(ih_server* s)
                         s->arena.release(rp->work_off, rp->work_bytes);
                         s->arena.release(rp->ih_off, rp->ih_bytes);
                         rp->status = st;
+                        rp->detail = ih_last_error();
                         rp->done = true;
                         rp->t.t_done_ns = now_ns();
                         s->admitted -= 1;
@@ -596,7 +601,9 @@ ih_status ih_poll(ih_server* s, uint64_t ticket, uint32_t* hists_host, ih_timing
     const ih_status st = r->status;
     if (st == IH_OK && hists_host && r->nq) std::memcpy(hists_host, r->hists_h, r->nq * r->B * 4);
     release_pinned(s, *r);
-    if (st != IH_OK) return fail(st, "request %llu failed: %s", (unsigned long long)ticket, ih_status_str(st));
+    if (st != IH_OK)
+        return fail(st, "request %llu failed: %s (%s)", (unsigned long long)ticket, ih_status_str(st),
+                    r->detail.c_str());
     return IH_OK;
 }
 
