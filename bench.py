@@ -47,7 +47,21 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the replayed 16-stream arrival trace (0: skip the serving leg)")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only run four 1 GiB device-to-device copies (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_reference(torch) -> None:
+    """Four copies of 1 GiB between two device buffers: each reads and writes
+    exactly 2^30 bytes, which is what FETCH_SIZE / WRITE_SIZE should report
+    for one such dispatch."""
+    src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": 1 << 30, "dispatches": 4}), flush=True)
 
 
 def log(msg):
@@ -257,6 +271,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_reference:
+        copy_reference(torch)
+        return
     from paper_1711_01919_amd import binding as ihb
     from paper_1711_01919_amd import synth
     import oracle

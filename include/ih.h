@@ -127,7 +127,9 @@ typedef struct {
                                process and, if IH_AUTOTUNE_CACHE names a file, on
                                disk); 0: built-in heuristic                         */
     int32_t use_graph;      /* 1: capture the launches in hipGraphs (default)        */
-    int32_t tile_x, tile_y; /* both > 0: force this tile on every frame              */
+    int32_t tile_x, tile_y; /* both > 0: force this tile on every frame; tile_x is
+                               32 for any B, 64 for B <= 128, 128 for B == 64;
+                               1 <= tile_y <= 65535 (else IH_ERR_INVALID_ARG)     */
     int32_t nontemporal;    /* -1: as chosen; 0: regular stores; 1: non-temporal     */
 } ih_batch_options;
 

@@ -175,7 +175,7 @@ void save_cache(TuneCache& c)
 std::vector<ih::TileChoice> candidates(int32_t B)
 {
     std::vector<ih::TileChoice> c;
-    for (int tx : {32, 64})
+    for (int tx : {32, 64, 128})
         for (int ty : {16, 32, 64, 128, 256})
             for (bool nt : {false, true}) {
                 ih::TileChoice t{tx, ty, nt};
@@ -184,20 +184,28 @@ std::vector<ih::TileChoice> candidates(int32_t B)
     return c;
 }
 
-// Heuristic tile for frames of one bin count launched together: the widest
-// tile column of the bin class, and the tallest band (fewest carries) that
-// still leaves at least 8192 independent waves across all of the frames.
+// Heuristic tile for frames of one bin count launched together: the tallest
+// band (fewest carries) that still leaves at least 8192 independent waves
+// across all of the frames.  For B = 64, 128-wide tiles (half the left-carry
+// reads per stored byte) when a band of at least 64 rows still gives that
+// many waves; otherwise the single-frame tile width.
 ih::TileChoice batch_default_tile(const std::vector<ih_frame_desc>& descs, int32_t B)
 {
-    ih::TileChoice t = ih::default_tile(descs[0].H, descs[0].W, B);
-    for (int ty : {256, 128, 64, 32, 16}) {
-        int64_t waves = 0;
+    constexpr int64_t kMinWaves = 8192;
+    auto waves_of = [&](int tx, int ty) {
+        int64_t w = 0;
         for (const ih_frame_desc& d : descs) {
-            const ih::Geom g = ih::make_geom(d.H, d.W, d.B, ih::TileChoice{t.TX, ty, false});
-            waves += (int64_t)g.nTY * g.nJG;
+            const ih::Geom g = ih::make_geom(d.H, d.W, d.B, ih::TileChoice{tx, ty, false});
+            w += (int64_t)g.nTY * g.nJG;
         }
+        return w;
+    };
+    ih::TileChoice t = ih::default_tile(descs[0].H, descs[0].W, B);
+    if (ih::tile_supported(B, ih::TileChoice{128, 64, false}) && waves_of(128, 64) >= kMinWaves)
+        t.TX = 128;
+    for (int ty : {256, 128, 64, 32, 16}) {
         t.TY = ty;
-        if (waves >= 8192) break;
+        if (waves_of(t.TX, ty) >= kMinWaves) break;
     }
     return t;
 }

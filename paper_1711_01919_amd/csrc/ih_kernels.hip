@@ -86,7 +86,7 @@ __device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs,
 // ---------------------------------------------------------------------------
 // One wave per frame row.  For a chunk of up to kSegChunk tile segments the
 // wave bins the row's pixels into per-segment histograms in LDS (8-bit
-// counters: a segment holds at most TX <= 64 pixels), then each lane walks
+// counters: a segment holds at most TX <= 128 pixels), then each lane walks
 // the segments for its bins and stores the exclusive running count: rowc[y][j][b]
 // = pixels of row y left of segment j in bin b.
 constexpr int kSegChunk = 64;
@@ -249,11 +249,15 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     }
 }
 
+// Largest B that a TX-wide tile supports (128-wide tiles are for B = 64).
+template <int TX>
+constexpr int agg_max_bins() { return TX == 128 ? 64 : 256; }
+
 template <int TX>
 __global__ __launch_bounds__(kAggThreads)
 void agg_kernel(FrameArgs f)
 {
-    __shared__ uint32_t colh[TX * 256 / 2];
+    __shared__ uint32_t colh[TX * agg_max_bins<TX>() / 2];
     agg_body<TX>(f, blockIdx.x, colh);
 }
 
@@ -261,7 +265,7 @@ template <int TX>
 __global__ __launch_bounds__(kAggThreads)
 void agg_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
-    __shared__ uint32_t colh[TX * 256 / 2];
+    __shared__ uint32_t colh[TX * agg_max_bins<TX>() / 2];
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
     agg_body<TX>(f, (int64_t)blockIdx.x - jb.begin, colh);
@@ -633,7 +637,10 @@ bool tile_supported(int32_t B, const TileChoice& t)
     const int bpl = bins_per_lane(B);
     if (t.TY < 1 || t.TY > 65535) return false;
     if (bpl == 4) return t.TX == 32;
-    return t.TX == 32 || t.TX == 64;
+    if (bpl == 2) return t.TX == 32 || t.TX == 64;
+    // 128 columns of accumulators fit the register file only with one
+    // segment per wave and compile-time B
+    return t.TX == 32 || t.TX == 64 || (t.TX == 128 && B == 64);
 }
 
 TileChoice default_tile(int32_t H, int32_t W, int32_t B)
@@ -721,7 +728,9 @@ template <bool NT, bool GUARD>
 static TileFns pick_v(const TileVariant& v)
 {
     switch (v.bpl) {
-    case 1: return v.tx == 32 ? pick_bc<1, 32, NT, GUARD>(v.bc) : pick_bc<1, 64, NT, GUARD>(v.bc);
+    case 1:
+        if (v.tx == 128) return fns_of<1, 128, 64, NT, GUARD>();      // B == 64 only
+        return v.tx == 32 ? pick_bc<1, 32, NT, GUARD>(v.bc) : pick_bc<1, 64, NT, GUARD>(v.bc);
     case 2: return v.tx == 32 ? pick_bc<2, 32, NT, GUARD>(v.bc) : pick_bc<2, 64, NT, GUARD>(v.bc);
     default: return pick_bc<4, 32, NT, GUARD>(v.bc);
     }
@@ -756,6 +765,8 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
         const unsigned ntiles = (unsigned)g.nTX * (unsigned)g.nTY;
         if (g.TX == 32)
             hipLaunchKernelGGL(agg_kernel<32>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
+        else if (g.TX == 128)
+            hipLaunchKernelGGL(agg_kernel<128>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
         else
             hipLaunchKernelGGL(agg_kernel<64>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
         break;
@@ -791,6 +802,9 @@ hipError_t launch_agg_batch(int TX, const FrameArgs* frames, const Job* jobs, in
     if (nblocks <= 0) return hipSuccess;
     if (TX == 32)
         hipLaunchKernelGGL(agg_batch_kernel<32>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,
+                           frames, jobs, njobs);
+    else if (TX == 128)
+        hipLaunchKernelGGL(agg_batch_kernel<128>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,
                            frames, jobs, njobs);
     else
         hipLaunchKernelGGL(agg_batch_kernel<64>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,

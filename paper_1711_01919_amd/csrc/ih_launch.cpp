@@ -61,7 +61,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         tables.push_back(std::move(jobs));
     }
 
-    for (int tx : {32, 64}) {
+    for (int tx : {32, 64, 128}) {
         std::vector<Job> jobs;
         int64_t begin = 0;
         for (size_t k = 0; k < n; ++k) {

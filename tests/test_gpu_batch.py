@@ -38,7 +38,7 @@ def test_uneven_batch_small(ihb, orc):
     plan.close()
 
 
-CANDIDATES = [(tx, ty, nt) for tx in (32, 64) for ty in (16, 32, 64, 128, 256) for nt in (0, 1)]
+CANDIDATES = [(tx, ty, nt) for tx in (32, 64, 128) for ty in (16, 32, 64, 128, 256) for nt in (0, 1)]
 
 
 @pytest.mark.parametrize("tx,ty,nt", CANDIDATES)
@@ -46,6 +46,8 @@ def test_every_tile_candidate(ihb, orc, tx, ty, nt):
     """Each tile shape and store flavour the autotuner can choose."""
     rng = np.random.default_rng(tx * 1000 + ty + nt)
     shapes = [(300, 257, 64), (128, 640, 32), (97, 130, 128), (64, 192, 16), (50, 70, 3), (1, 64, 7)]
+    if tx == 128:                                       # B = 64 only: whole, ragged and narrow frames
+        shapes = [(300, 257, 64), (33, 384, 64), (17, 130, 64), (1, 64, 64), (5, 1, 64)]
     if tx == 32:
         shapes.append((70, 96, 256))
     frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _ in shapes]
@@ -109,7 +111,7 @@ def test_autotuned_plan(ihb, orc):
     torch.cuda.synchronize()
     for k in range(4):
         tx, ty, _ = plan.frame_tile(k)
-        assert tx in (32, 64) and ty in (16, 32, 64, 128, 256)
+        assert tx in (32, 64, 128) and ty in (16, 32, 64, 128, 256)
         assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(frames[k], bins[k]))
     plan.close()
 
@@ -145,3 +147,9 @@ def test_bad_descriptors_rejected(ihb):
     o256 = torch.zeros((8, 8, 256), dtype=torch.uint32, device="cuda")
     with pytest.raises(ihb.IHError):
         ihb.BatchPlan([f], [o256], [256], tile=(64, 16))        # B > 128 needs 32-wide tiles
+    o128 = torch.zeros((8, 8, 128), dtype=torch.uint32, device="cuda")
+    with pytest.raises(ihb.IHError):
+        ihb.BatchPlan([f], [o128], [128], tile=(128, 16))       # 128-wide tiles need B = 64
+    o32 = torch.zeros((8, 8, 32), dtype=torch.uint32, device="cuda")
+    with pytest.raises(ihb.IHError):
+        ihb.BatchPlan([f], [o32], [32], tile=(128, 16))
