@@ -8,7 +8,9 @@ bins (seeded synthetic stand-in for the paper's HD video), every frame's
 integral histogram computed into its own resident H x W x B uint32 tensor
 (64 x 530.8 MB = 34 GB of output per step) by ONE launch of a batched plan
 (a hipGraph holding one launch per phase for all 64 frames).  Inputs are
-resident in HBM before the timed region starts.
+resident in HBM before the timed region starts.  The same frames also go
+through a pipelined plan (4 GiB groups, each group's carry phases on a
+second stream beside the previous group's tile pass) for comparison.
 
 Prints ONE JSON line: throughput (entries/s) of the batched step; the same
 frames through 64 plain per-frame ih_compute calls for comparison; the
@@ -30,6 +32,31 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per tile-pass launch of the 64-frame step, from two rocprofv3 --pmc
+# runs (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the factors a 1 GiB device copy
+# reads on the same counters).  Valid only for the kernel source and tile they
+# were taken with; any other combination reports null.
+TRAFFIC_RECORD = {
+    "kernel_src_sha256": "886f746434039841b6ec3696ade4bf7963bed2f11dcc823dfc354d53fa78b69b",
+    "workload": "disc_sequence_64x1080x1920_B64", "tile": [128, 128], "nontemporal": False,
+    "fetch_bytes": 399970.3 * 2.0 * 1024, "write_bytes": 33177600.0 * 1.0 * 1024,
+}
+
+
+def recorded_traffic(workload: str, tile) -> float | None:
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1711_01919_amd", "csrc", "ih_kernels.hip")
+    try:
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    r = TRAFFIC_RECORD
+    if (digest != r["kernel_src_sha256"] or workload != r["workload"]
+            or list(tile[:2]) != r["tile"] or bool(tile[2]) != r["nontemporal"]):
+        return None
+    return r["fetch_bytes"] + r["write_bytes"]
 METRIC = "integral-hist entries/s + % HBM peak; served p50/p99 latency vs plain loop"
 
 
@@ -41,6 +68,8 @@ def parse():
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the 64-frame plan (default: the batch heuristic tile)")
+    ap.add_argument("--group-bytes", type=int, default=0,
+                    help="pipeline group size of the 64-frame plan in output bytes (<= 0: one group)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 256-frame uneven batch leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample")
@@ -291,7 +320,7 @@ def main():
 
     t0 = time.time()
     plan = ihb.BatchPlan([d_frames[k] for k in range(n)], outs, [B] * n,
-                         autotune=args.autotune, stream=stream)
+                         autotune=args.autotune, stream=stream, group_bytes=args.group_bytes)
     tile = plan.frame_tile(0)
     info = plan.info()
     log(f"[bench] plan ready in {time.time() - t0:.1f}s: tile {tile}, {info}")
@@ -301,19 +330,23 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({args.warmup} steps)")
 
-    ihb.profile_enable(True)
+    # timed region: K plan launches exactly as a caller makes them (one graph
+    # launch each), then K more with the per-phase event profiler on, which
+    # brackets every tile-pass launch with HIP events on its own stream
     ms_total = timed(torch, stream, lambda: plan.launch(stream), args.steps)
+    ihb.profile_enable(True)
+    ms_prof = timed(torch, stream, lambda: plan.launch(stream), args.steps)
     ph = ihb.profile_read()
     ihb.profile_enable(False)
-    log(f"[bench] timed {args.steps} batched steps: {ms_total:.2f} ms; phases {ph}")
+    log(f"[bench] timed {args.steps} batched steps: {ms_total:.2f} ms; profiled: {ms_prof:.2f} ms, phases {ph}")
 
     ms_step = ms_total / args.steps
     entries_step = n * H * W * B
     alg_bytes_frame = H * W + 4 * H * W * B                   # frame read + output written
     value = entries_step / (ms_step / 1e3)
-    launches = args.steps                                     # one tile launch per step
+    launches = args.steps * info["tile_launches"]             # tile-pass kernels in the profiled steps
     tile_ms_launch = ph["tile_ms"] / launches
-    alg_bytes_launch = n * alg_bytes_frame
+    alg_bytes_launch = n * alg_bytes_frame / info["tile_launches"]
     achieved = alg_bytes_launch / (tile_ms_launch / 1e3) / 1e9
     step_gbs = n * alg_bytes_frame / (ms_step / 1e3) / 1e9
 
@@ -331,6 +364,19 @@ def main():
     plain_steps = max(2, min(args.steps, 10))
     ms_plain = timed(torch, stream, plain_step, plain_steps) / plain_steps
     log(f"[bench] plain loop: {ms_plain:.3f} ms/step")
+
+    # the same frames through a pipelined plan (4 GiB groups, carries of the
+    # next group on a second stream)
+    pplan = ihb.BatchPlan([d_frames[k] for k in range(n)], outs, [B] * n, stream=stream,
+                          group_bytes=4 << 30)
+    pinfo = pplan.info()
+    for _ in range(max(1, args.warmup)):
+        pplan.launch(stream)
+    ms_pipe = timed(torch, stream, lambda: pplan.launch(stream), args.steps) / args.steps
+    pipelined = {"ms_per_step": ms_pipe, "value": entries_step / (ms_pipe / 1e3), "groups": pinfo["groups"],
+                 "tile": list(pplan.frame_tile(0))}
+    pplan.close()
+    log(f"[bench] pipelined plan: {pipelined}")
 
 
     plan.close()
@@ -354,14 +400,18 @@ def main():
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"disc_sequence_{n}x{H}x{W}_B{B}", "frames": n, "H": H, "W": W, "B": B,
                    "form": "batched_graph", "tile": list(tile[:2]), "nontemporal": tile[2],
-                   "parallelism": "single_gpu"},
+                   "pipeline_groups": info["groups"], "parallelism": "single_gpu"},
         "hbm_frac_step": step_gbs / HBM_PEAK_GBS,
         "plain_loop": {"value": entries_step / (ms_plain / 1e3), "ms_per_step": ms_plain,
                        "speedup_batched": ms_plain / ms_step},
+        "profiled_ms_per_step": ms_prof / args.steps,
+        "pipelined_4GiB": pipelined,
         "phase_ms_per_step": {k: ph[k] / args.steps for k in ("agg_ms", "scan_ms", "tile_ms")},
         "roofline": {"bound": "hbm", "kernel": "tile_batch_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes_per_launch": alg_bytes_launch},
+                     "traffic": recorded_traffic(f"disc_sequence_{n}x{H}x{W}_B{B}", tile),
+                     "alg_bytes_per_launch": alg_bytes_launch,
+                     "launches": launches, "avg_launch_us": tile_ms_launch * 1e3},
     }
     rec.update(legs)
     if served is not None:

@@ -131,6 +131,13 @@ typedef struct {
                                32 for any B, 64 for B <= 128, 128 for B == 64;
                                1 <= tile_y <= 65535 (else IH_ERR_INVALID_ARG)     */
     int32_t nontemporal;    /* -1: as chosen; 0: regular stores; 1: non-temporal     */
+    int64_t group_bytes;    /* > 0: pipelining.  Frames (in the order given) are
+                               split into groups of about this many output bytes
+                               (at least two groups, at most one per frame); a
+                               group's carries are computed on a second stream
+                               while the previous group's tile pass runs, so the
+                               tile pass finds them in cache.  <= 0: one group,
+                               all phases in order (default)                     */
 } ih_batch_options;
 
 typedef struct ih_batch_plan ih_batch_plan;
@@ -141,6 +148,7 @@ typedef struct {
     int32_t kernel_launches; /* kernels per plan launch (all phases)                */
     int32_t tile_launches;   /* of which tile-pass kernels (one per kernel variant) */
     int32_t graph;           /* 1 if replayed from a hipGraph                        */
+    int32_t groups;          /* pipeline groups (1: not pipelined)                  */
 } ih_batch_info;
 
 /*
@@ -150,15 +158,18 @@ typedef struct {
  * scratch (about (1/TX + 1/TY) of the total output) and job tables, and
  * captures the launches.  Autotuning runs candidate launches on `stream`,
  * writing the frames' outputs, and synchronizes it.  opt may be NULL
- * (defaults: no autotune, graph on, heuristic tiles).
+ * (defaults: no autotune, graph on, heuristic tiles, one group).
  * Errors: IH_ERR_INVALID_ARG, IH_ERR_RANGE, IH_ERR_OOM, IH_ERR_HIP.
  */
 ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_batch_options* opt,
                                ih_stream_t stream, ih_batch_plan** plan);
 
 /* Enqueue every frame's integral histogram on `stream` (one graph launch; one
- * per phase while ih_profile_enable is on).  Plans may be launched repeatedly;
- * launches of one plan on different streams must not overlap. */
+ * per phase, or direct launches for a pipelined plan, while ih_profile_enable
+ * is on).  A pipelined plan also runs work on a stream of its own, ordered
+ * after everything enqueued on `stream` before the call; everything the call
+ * enqueues completes before later work on `stream`.  Plans may be launched
+ * repeatedly; launches of one plan on different streams must not overlap. */
 ih_status ih_batch_plan_launch(ih_batch_plan* plan, ih_stream_t stream);
 
 /* Synchronizes the device, then frees the plan's scratch, tables and graphs. */

@@ -52,12 +52,12 @@ class FrameDesc(ctypes.Structure):
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+                ("tile_y", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("group_bytes", ctypes.c_int64)]
 
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_int64), ("entries", ctypes.c_int64), ("kernel_launches", ctypes.c_int32),
-                ("tile_launches", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("tile_launches", ctypes.c_int32), ("graph", ctypes.c_int32), ("groups", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -195,7 +195,9 @@ class BatchPlan:
     keeps references to them."""
 
     def __init__(self, frames, outs, bins, autotune=False, use_graph=True, tile=None,
-                 nontemporal=-1, stream=None):
+                 nontemporal=-1, stream=None, group_bytes=0):
+        """group_bytes > 0 pipelines the plan in groups of about that many
+        output bytes (see ih_batch_options in include/ih.h)."""
         if not (len(frames) == len(outs) == len(bins)) or len(frames) == 0:
             raise ValueError("frames, outs and bins must be equally long and non-empty")
         descs = (FrameDesc * len(frames))()
@@ -207,7 +209,8 @@ class BatchPlan:
                 raise ValueError(f"out {k} must be a contiguous uint32 CUDA tensor with H*W*B elements")
             descs[k] = FrameDesc(_ptr(f), _ptr(o), H, W, int(b))
         tx, ty = tile if tile else (0, 0)
-        opt = BatchOptions(1 if autotune else 0, 1 if use_graph else 0, tx, ty, int(nontemporal))
+        opt = BatchOptions(1 if autotune else 0, 1 if use_graph else 0, tx, ty, int(nontemporal),
+                           int(group_bytes))
         h = ctypes.c_void_p()
         _check(lib.ih_batch_plan_create(descs, len(frames), ctypes.byref(opt), _stream_handle(stream),
                                         ctypes.byref(h)), "ih_batch_plan_create")
@@ -221,7 +224,7 @@ class BatchPlan:
         i = BatchInfo()
         _check(lib.ih_batch_plan_info(self._h, ctypes.byref(i)), "ih_batch_plan_info")
         return {"frames": i.frames, "entries": i.entries, "kernel_launches": i.kernel_launches,
-                "tile_launches": i.tile_launches, "graph": bool(i.graph)}
+                "tile_launches": i.tile_launches, "graph": bool(i.graph), "groups": i.groups}
 
     def frame_tile(self, k: int):
         tx, ty, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

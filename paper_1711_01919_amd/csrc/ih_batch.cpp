@@ -27,13 +27,25 @@ using ih::hip_fail;
 
 }  // namespace
 
+// A pipeline group: consecutive frames of the plan with their own launch
+// image (job tables indexed by the group's frames).
+struct PlanGroup {
+    ih::BatchImage image;
+    size_t dev_off = 0;         // byte offset of the image in the plan's device tables
+};
+
 struct ih_batch_plan {
     int device = 0;
     std::vector<ih_frame_desc> descs;
     std::vector<ih::TileChoice> tiles;
     void* d_scratch = nullptr;
     void* d_image = nullptr;
-    ih::BatchImage image;
+    ih::BatchImage image;                 // one group: every frame
+    std::vector<PlanGroup> groups;        // two or more: the pipelined form
+    int64_t group_bytes = 0;              // requested (options), resolved at build
+    hipStream_t side = nullptr;           // pipelined form: carry phases run here
+    std::vector<hipEvent_t> ev_carry, ev_tile;
+    hipEvent_t ev_start = nullptr;
     bool use_graph = true;
     hipGraphExec_t exec_all = nullptr;
     hipGraphExec_t exec_phase[ih::kNumPhases] = {nullptr, nullptr, nullptr};
@@ -42,10 +54,41 @@ struct ih_batch_plan {
 
 namespace {
 
-// Enqueue the launches of the given phase (-1: all), in order.
+// Enqueue the launches of the given phase (-1: all), in order.  Not for
+// pipelined plans.
 hipError_t enqueue(const ih_batch_plan* p, int phase, hipStream_t s)
 {
     return ih::enqueue_batch(p->image, p->d_image, phase, s);
+}
+
+// The pipelined form.  Group g's carry phases run on the side stream after
+// group g-1's carries and after group g-2's tile pass (so at most two groups'
+// carries are live in cache); its tile pass runs on s after group g-1's tile
+// pass and its own carries.  The side stream first waits for everything
+// already on s, and s ends after the last group's tile pass, which follows
+// every carry launch.  With timed, each phase is bracketed by events.
+hipError_t enqueue_pipelined(const ih_batch_plan* p, hipStream_t s, bool timed, ih_status* tst)
+{
+    const unsigned char* dev = static_cast<const unsigned char*>(p->d_image);
+    hipError_t e = hipEventRecord(p->ev_start, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_start, 0);
+    ih::PhaseTimer ts, tm;
+    for (size_t g = 0; e == hipSuccess && g < p->groups.size(); ++g) {
+        const PlanGroup& G = p->groups[g];
+        if (g >= 2) e = hipStreamWaitEvent(p->side, p->ev_tile[g - 2], 0);
+        for (int ph = 0; e == hipSuccess && ph < 2; ++ph) {
+            if (timed && (*tst = ts.begin(ph, p->side)) != IH_OK) return hipSuccess;
+            e = ih::enqueue_batch(G.image, dev + G.dev_off, ph, p->side);
+            if (e == hipSuccess && timed && (*tst = ts.end(p->side)) != IH_OK) return hipSuccess;
+        }
+        if (e == hipSuccess) e = hipEventRecord(p->ev_carry[g], p->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_carry[g], 0);
+        if (e == hipSuccess && timed && (*tst = tm.begin(2, s)) != IH_OK) return hipSuccess;
+        if (e == hipSuccess) e = ih::enqueue_batch(G.image, dev + G.dev_off, 2, s);
+        if (e == hipSuccess && timed && (*tst = tm.end(s)) != IH_OK) return hipSuccess;
+        if (e == hipSuccess) e = hipEventRecord(p->ev_tile[g], s);
+    }
+    return e;
 }
 
 void free_plan(ih_batch_plan* p)
@@ -54,9 +97,21 @@ void free_plan(ih_batch_plan* p)
     if (p->exec_all) (void)hipGraphExecDestroy(p->exec_all);
     for (auto& e : p->exec_phase)
         if (e) (void)hipGraphExecDestroy(e);
+    for (hipEvent_t e : p->ev_carry) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->ev_tile) (void)hipEventDestroy(e);
+    if (p->ev_start) (void)hipEventDestroy(p->ev_start);
+    if (p->side) (void)hipStreamDestroy(p->side);
     if (p->d_image) (void)hipFree(p->d_image);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     delete p;
+}
+
+// Number of pipeline groups for a batch of total_out output bytes (at least
+// two when pipelining is asked for).
+int64_t group_count(int64_t total_out, int64_t group_bytes)
+{
+    if (group_bytes <= 0) return 1;
+    return std::max<int64_t>(2, (total_out + group_bytes - 1) / group_bytes);
 }
 
 // Lay out scratch, build the launch image and upload it.  Frames keep the
@@ -81,19 +136,66 @@ ih_status build_plan(ih_batch_plan* p)
     }
     std::vector<ih::FrameArgs> frames(n);
     std::vector<char> nt(n);
+    int64_t total_out = 0;
     for (size_t k = 0; k < n; ++k) {
         frames[k] = ih::frame_args(p->descs[k].frame, p->descs[k].out,
                                    static_cast<uint32_t*>(p->d_scratch) + off[k], geoms[k]);
         nt[k] = p->tiles[k].nontemporal ? 1 : 0;
+        total_out += (int64_t)p->descs[k].H * p->descs[k].W * p->descs[k].B * 4;
     }
-    ih::build_batch_image(frames, nt, &p->image);
-    e = hipMalloc(&p->d_image, p->image.bytes());
+    const int64_t ng = std::min<int64_t>(group_count(total_out, p->group_bytes), (int64_t)n);
+    if (ng <= 1) {
+        ih::build_batch_image(frames, nt, &p->image);
+        e = hipMalloc(&p->d_image, p->image.bytes());
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(IH_ERR_OOM, "batch tables: %s", hipGetErrorString(e));
+        }
+        e = hipMemcpy(p->d_image, p->image.host.data(), p->image.bytes(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload batch tables");
+        return IH_OK;
+    }
+    // Consecutive frames, group boundaries where the running output passes
+    // total * (g + 1) / ng; every group holds at least one frame.
+    size_t k0 = 0, bytes = 0;
+    int64_t acc = 0;
+    for (int64_t g = 0; g < ng && k0 < n; ++g) {
+        const int64_t goal = total_out / ng * (g + 1);
+        size_t k1 = k0;
+        do {
+            acc += (int64_t)p->descs[k1].H * p->descs[k1].W * p->descs[k1].B * 4;
+            ++k1;
+        } while (k1 < n && (acc < goal || g == ng - 1) && (int64_t)(n - k1) > ng - 1 - g);
+        PlanGroup G;
+        std::vector<ih::FrameArgs> sub(frames.begin() + k0, frames.begin() + k1);
+        std::vector<char> subnt(nt.begin() + k0, nt.begin() + k1);
+        ih::build_batch_image(sub, subnt, &G.image, true);
+        G.dev_off = bytes;
+        bytes = ih::align_up(bytes + G.image.bytes(), 256);
+        p->groups.push_back(std::move(G));
+        k0 = k1;
+    }
+    e = hipMalloc(&p->d_image, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(IH_ERR_OOM, "batch tables: %s", hipGetErrorString(e));
     }
-    e = hipMemcpy(p->d_image, p->image.host.data(), p->image.bytes(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "upload batch tables");
+    for (const PlanGroup& G : p->groups) {
+        e = hipMemcpy(static_cast<unsigned char*>(p->d_image) + G.dev_off, G.image.host.data(), G.image.bytes(),
+                      hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload batch tables");
+    }
+    e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    e = hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming);
+    for (size_t g = 0; e == hipSuccess && g < p->groups.size(); ++g) {
+        hipEvent_t a = nullptr, b = nullptr;
+        e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+        if (e == hipSuccess) p->ev_carry.push_back(a);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+        if (e == hipSuccess) p->ev_tile.push_back(b);
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     return IH_OK;
 }
 
@@ -105,7 +207,8 @@ ih_status capture(ih_batch_plan* p, int phase, hipGraphExec_t* out)
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = enqueue(p, phase, cs);
+        ih_status unused = IH_OK;
+        hipError_t e1 = p->groups.empty() ? enqueue(p, phase, cs) : enqueue_pipelined(p, cs, false, &unused);
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         e = e1 != hipSuccess ? e1 : e2;
     }
@@ -185,13 +288,13 @@ std::vector<ih::TileChoice> candidates(int32_t B)
 }
 
 // Heuristic tile for frames of one bin count launched together: the tallest
-// band (fewest carries) that still leaves at least 8192 independent waves
-// across all of the frames.  For B = 64, 128-wide tiles (half the left-carry
-// reads per stored byte) when a band of at least 64 rows still gives that
-// many waves; otherwise the single-frame tile width.
-ih::TileChoice batch_default_tile(const std::vector<ih_frame_desc>& descs, int32_t B)
+// band (fewest carries) that still leaves at least kMinWaves independent
+// waves across all of the frames.  For B = 64, 128-wide tiles (half the
+// left-carry reads per stored byte) when a band of at least 32 rows still
+// gives that many waves; otherwise the single-frame tile width.
+ih::TileChoice batch_default_tile(const std::vector<ih_frame_desc>& descs, int32_t B,
+                                  int64_t kMinWaves = 8192)
 {
-    constexpr int64_t kMinWaves = 8192;
     auto waves_of = [&](int tx, int ty) {
         int64_t w = 0;
         for (const ih_frame_desc& d : descs) {
@@ -201,7 +304,7 @@ ih::TileChoice batch_default_tile(const std::vector<ih_frame_desc>& descs, int32
         return w;
     };
     ih::TileChoice t = ih::default_tile(descs[0].H, descs[0].W, B);
-    if (ih::tile_supported(B, ih::TileChoice{128, 64, false}) && waves_of(128, 64) >= kMinWaves)
+    if (ih::tile_supported(B, ih::TileChoice{128, 32, false}) && waves_of(128, 32) >= kMinWaves)
         t.TX = 128;
     for (int ty : {256, 128, 64, 32, 16}) {
         t.TY = ty;
@@ -218,6 +321,7 @@ ih_status time_candidate(const std::vector<ih_frame_desc>& descs, const ih::Tile
     p->descs = descs;
     p->tiles.assign(descs.size(), t);
     p->use_graph = false;
+    p->group_bytes = -1;
     ih_status st = build_plan(p);
     hipEvent_t a = nullptr, b = nullptr;
     if (st == IH_OK) {
@@ -293,7 +397,7 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     *plan = nullptr;
     if (n == 0 || !frames) return fail(IH_ERR_INVALID_ARG, "need at least one frame");
     if (n > (1u << 20)) return fail(IH_ERR_RANGE, "too many frames (%zu)", n);
-    ih_batch_options o{0, 1, 0, 0, -1};
+    ih_batch_options o{0, 1, 0, 0, -1, 0};
     if (opt) o = *opt;
     const bool forced = o.tile_x > 0 || o.tile_y > 0;
     for (size_t k = 0; k < n; ++k) {
@@ -308,7 +412,11 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     (void)hipGetDevice(&p->device);
     p->descs.assign(frames, frames + n);
     p->use_graph = o.use_graph != 0;
+    p->group_bytes = o.group_bytes;
     p->tiles.resize(n);
+    int64_t total_out = 0;
+    for (size_t k = 0; k < n; ++k) total_out += (int64_t)frames[k].H * frames[k].W * frames[k].B * 4;
+    const int64_t ng = std::min<int64_t>(group_count(total_out, o.group_bytes), (int64_t)n);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ih_status st = IH_OK;
     if (forced) {
@@ -319,7 +427,15 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
         std::map<int32_t, std::vector<ih_frame_desc>> by_b;
         for (size_t k = 0; k < n; ++k) by_b[frames[k].B].push_back(frames[k]);
         std::map<int32_t, ih::TileChoice> choice;
-        for (auto& kv : by_b) choice[kv.first] = batch_default_tile(kv.second, kv.first);
+        // Pipelined: at least 1792 waves per group (about two per SIMD of a
+        // 256-CU device) for its tile pass, so bands stay tall and the two
+        // live groups' carries small; non-temporal stores so the output
+        // stream leaves the carries in cache.
+        const int64_t min_waves = ng > 1 ? 1792 * ng : 8192;
+        for (auto& kv : by_b) {
+            choice[kv.first] = batch_default_tile(kv.second, kv.first, min_waves);
+            choice[kv.first].nontemporal = ng > 1;
+        }
         for (size_t k = 0; k < n; ++k) p->tiles[k] = choice[frames[k].B];
     }
     if (st == IH_OK && o.nontemporal >= 0)
@@ -327,7 +443,8 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     if (st == IH_OK) st = build_plan(p);
     if (st == IH_OK && p->use_graph) {
         st = capture(p, -1, &p->exec_all);
-        for (int ph = 0; st == IH_OK && ph < ih::kNumPhases; ++ph) st = capture(p, ph, &p->exec_phase[ph]);
+        for (int ph = 0; st == IH_OK && p->groups.empty() && ph < ih::kNumPhases; ++ph)
+            st = capture(p, ph, &p->exec_phase[ph]);
     }
     if (st != IH_OK) {
         free_plan(p);
@@ -343,6 +460,14 @@ ih_status ih_batch_plan_launch(ih_batch_plan* p, ih_stream_t stream)
     hipStream_t s = static_cast<hipStream_t>(stream);
     ih::PhaseTimer timer;
     const bool prof = ih::profiling_on();
+    if (!p->groups.empty()) {
+        ih_status tst = IH_OK;
+        hipError_t e = p->use_graph && !prof ? hipGraphLaunch(p->exec_all, s) : enqueue_pipelined(p, s, prof, &tst);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+        if (tst != IH_OK) return tst;
+        if (prof) ih::profiling_add_frames((uint64_t)p->descs.size());
+        return IH_OK;
+    }
     if (!prof) {
         hipError_t e = p->use_graph ? hipGraphLaunch(p->exec_all, s) : enqueue(p, -1, s);
         if (e != hipSuccess) return hip_fail(e, "batch launch");
@@ -372,10 +497,16 @@ ih_status ih_batch_plan_info(const ih_batch_plan* p, ih_batch_info* info)
     if (!p || !info) return fail(IH_ERR_INVALID_ARG, "plan and info must be non-null");
     info->frames = (int64_t)p->descs.size();
     info->entries = p->entries;
-    info->kernel_launches = (int32_t)p->image.launches.size();
     info->graph = p->use_graph ? 1 : 0;
-    int32_t tile_launches = 0;
-    for (const ih::BatchLaunch& l : p->image.launches) tile_launches += l.kind == ih::BatchLaunch::kTile;
+    info->groups = p->groups.empty() ? 1 : (int32_t)p->groups.size();
+    int32_t launches = 0, tile_launches = 0;
+    auto count = [&](const ih::BatchImage& img) {
+        launches += (int32_t)img.launches.size();
+        for (const ih::BatchLaunch& l : img.launches) tile_launches += l.kind == ih::BatchLaunch::kTile;
+    };
+    if (p->groups.empty()) count(p->image);
+    for (const PlanGroup& G : p->groups) count(G.image);
+    info->kernel_launches = launches;
     info->tile_launches = tile_launches;
     return IH_OK;
 }

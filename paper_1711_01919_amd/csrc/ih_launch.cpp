@@ -36,8 +36,25 @@ static int32_t resident_blocks_cached(const TileVariant& v)
     return r;
 }
 
+// Compute units of the current device, asked of the runtime once per device.
+static int32_t cu_count_cached()
+{
+    static std::mutex mu;
+    static std::map<int, int32_t>* cache = new std::map<int, int32_t>;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache->find(dev);
+    if (it != cache->end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    (*cache)[dev] = cus;
+    return cus;
+}
+
 void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<char>& nontemporal,
-                       BatchImage* img)
+                       BatchImage* img, bool leave_room)
 {
     const size_t n = frames.size();
     std::vector<std::vector<Job>> tables;
@@ -117,7 +134,13 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         l.n = items[kv.first];
         l.njobs = (int32_t)kv.second.size();
         const int64_t want = (l.n + kWavesPerBlock - 1) / kWavesPerBlock;
-        l.grid = (int32_t)std::min<int64_t>(want, resident_blocks_cached(kv.first));
+        int32_t cap = resident_blocks_cached(kv.first);
+        if (leave_room) {
+            const int32_t cus = cu_count_cached();
+            const int32_t per_cu = cap / cus;
+            if (per_cu >= 2) cap = (per_cu - 1) * cus;
+        }
+        l.grid = (int32_t)std::min<int64_t>(want, cap);
         launches.push_back(l);
         tables.push_back(std::move(kv.second));
     }

@@ -33,9 +33,11 @@ size_t align_up(size_t v, size_t a);
 size_t frame_scratch_words(const Geom& g);
 
 // Fill img from fully set-up frames (device pointers, scratch included).
-// nontemporal[k] picks the store flavour of frame k.
+// nontemporal[k] picks the store flavour of frame k.  With leave_room, the
+// persistent tile grid keeps one workgroup slot per compute unit free (when
+// the kernel fits two or more per unit) for kernels running beside it.
 void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<char>& nontemporal,
-                       BatchImage* img);
+                       BatchImage* img, bool leave_room = false);
 
 // Enqueue the image's launches of one phase (-1: all phases) on s.  dev_image
 // is a device copy of img.host that stays valid until the work has run.

@@ -99,6 +99,71 @@ def test_profiled_and_ungraphed_launches(ihb, orc):
         plan.close()
 
 
+@pytest.mark.parametrize("group_bytes,use_graph", [(1 << 20, True), (1 << 20, False), (1, True), (40 << 20, True)])
+def test_pipelined_groups(ihb, orc, group_bytes, use_graph):
+    """Frames split into pipeline groups (carries of group g+1 on a second
+    stream beside the tile pass of group g): graph replays with eager work
+    between them, direct launches, profiled launches, one frame per group
+    (group_bytes=1) and uneven groups all give the oracle's bits."""
+    rng = np.random.default_rng(24)
+    shapes = [(240, 320, 64), (97, 203, 32), (360, 640, 16), (61, 64, 128), (240, 320, 64), (130, 257, 7),
+              (480, 640, 64)]
+    frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _ in shapes]
+    bins = [b for _, _, b in shapes]
+    refs = [orc.integral_histogram(f, b) for f, b in zip(frames, bins)]
+    fr, outs = to_dev(frames, bins)
+    plan = ihb.BatchPlan(fr, outs, bins, use_graph=use_graph, group_bytes=group_bytes)
+    info = plan.info()
+    assert info["graph"] == use_graph
+    total = sum(h * w * b * 4 for h, w, b in shapes)
+    assert 2 <= info["groups"] <= len(frames)
+    if group_bytes == 1:
+        assert info["groups"] == len(frames)
+    else:
+        assert info["groups"] == min(len(frames), -(-total // group_bytes))
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        if rep == 2:
+            ihb.profile_enable(True)
+        plan.launch()
+        if rep == 2:
+            ph = ihb.profile_read()
+            ihb.profile_enable(False)
+            assert ph["frames"] == len(frames) and ph["tile_ms"] > 0 and ph["agg_ms"] > 0
+        torch.cuda.synchronize()
+        for k in range(len(frames)):
+            assert np.array_equal(outs[k].cpu().numpy(), refs[k]), (rep, k)
+    plan.close()
+
+
+def test_pipelined_launch_orders_after_stream_work(ihb, orc):
+    """Work enqueued on the launch stream before a pipelined launch (the frame
+    upload) is seen by the side stream's carry phases, and work after it sees
+    every output."""
+    rng = np.random.default_rng(25)
+    frames = [rng.integers(0, 256, size=(300, 400), dtype=np.uint8) for _ in range(6)]
+    bins = [64] * 6
+    fr = [torch.zeros((300, 400), dtype=torch.uint8, device="cuda") for _ in range(6)]
+    outs = [torch.empty((300, 400, 64), dtype=torch.uint32, device="cuda") for _ in range(6)]
+    s = torch.cuda.Stream()
+    plan = ihb.BatchPlan(fr, outs, bins, group_bytes=1 << 20, stream=s)
+    host = [torch.from_numpy(f).pin_memory() for f in frames]
+    sums = []
+    with torch.cuda.stream(s):
+        for d, h in zip(fr, host):
+            d.copy_(h, non_blocking=True)
+        plan.launch(s)
+        for o in outs:
+            sums.append(o[-1, -1].to(torch.int64).sum())
+    s.synchronize()
+    for k in range(6):
+        assert int(sums[k]) == 300 * 400
+        assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(frames[k], 64)), k
+    plan.close()
+
+
 def test_autotuned_plan(ihb, orc):
     rng = np.random.default_rng(23)
     frames = [rng.integers(0, 256, size=(360, 640), dtype=np.uint8) for _ in range(4)]
