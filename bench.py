@@ -16,7 +16,9 @@ Prints ONE JSON line: throughput (entries/s) of the batched step; the same
 frames through 64 plain per-frame ih_compute calls for comparison; the
 roofline of the dominant kernel (the tile pass, HBM-bound); the 640x480
 B=32 frame and the 8192x8192 B=128 frame through ih_compute with their
-region queries; the serving loop's p50/p99 latency and
+region queries; the host-transfer pipeline (frames/s with the whole integral
+histogram copied back over PCIe, as the paper measures); the serving loop's
+p50/p99 latency and
 throughput on a replayed 16-stream trace next to the plain per-frame path;
 and the single-threaded CPU oracle timed on a bounded sample of the batched
 workload.
@@ -71,6 +73,7 @@ def parse():
     ap.add_argument("--group-bytes", type=int, default=0,
                     help="pipeline group size of the 64-frame plan in output bytes (<= 0: one group)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 256-frame uneven batch leg")
+    ap.add_argument("--no-transfer", action="store_true", help="skip the host-transfer pipeline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,9 +117,40 @@ def cpu_baseline(frames: np.ndarray, B: int, budget_s: float) -> dict:
         assert rc == 0
         done += 1
     entries = done * H * W * B
-    return {"value": entries / t_total, "unit": "entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {frames.shape[0]} frames ({H}x{W}, B={B}), "
-                      f"{t_total:.1f} s single-threaded, {oracle.compile_flags()}, host has {os.cpu_count()} cpus"}
+    res = {"value": entries / t_total, "unit": "entries/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {done} of {frames.shape[0]} frames ({H}x{W}, B={B}), "
+                     f"{t_total:.1f} s single-threaded, {oracle.compile_flags()}, "
+                     f"host: {os.cpu_count()} cpus, {cpu_model()}"}
+    # frame-parallel, one oracle call per thread (the call releases the GIL),
+    # as the paper's multi-threaded CPU comparison
+    from concurrent.futures import ThreadPoolExecutor
+    threads = max(1, min(16, os.cpu_count() or 1))
+    outs = [np.zeros((H, W, B), dtype=np.uint32) for _ in range(threads)]
+    per_thread = max(1, min(frames.shape[0] // threads, int(budget_s / max(t_total / done, 1e-9))))
+
+    def work(t):
+        for k in range(per_thread):
+            f = np.ascontiguousarray(frames[(t * per_thread + k) % frames.shape[0]])
+            assert orc.lib.ihref_integral_histogram(f.ctypes.data_as(_u8p), H, W, B,
+                                                    outs[t].ctypes.data_as(_u32p)) == 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(work, range(threads)))
+    t_par = time.perf_counter() - t0
+    res["parallel"] = {"value": threads * per_thread * H * W * B / t_par, "cores": threads,
+                       "sample": f"{threads} threads x {per_thread} frames, {t_par:.1f} s"}
+    return res
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "cpu model unknown"
 
 
 def timed(torch, stream, fn, steps):
@@ -132,26 +166,32 @@ def timed(torch, stream, fn, steps):
 
 
 def plain_and_query_legs(torch, ihb, synth, stream) -> dict:
-    """The 640x480 B=32 frame through ih_compute (per-call time over many
-    calls) with its 1000 rectangles, and 1e6 rectangles on the 8192x8192
-    B=128 mixture frame; queries read rectangles already on the device.
+    """The 640x480 B=32 frame through ih_compute (mean over 1000 calls
+    rotating 8 outputs) with its 1000 rectangles, and the 8192x8192 B=128
+    mixture frame with 1e6 rectangles; queries read rectangles already on the
+    device.
     Algorithmic query bytes: 4 corners x B x 4 read + B x 4 written = 20*B
     per rectangle."""
     out = {}
     I, B, rects = synth.plain_frame()
     H, W = I.shape
     f = torch.from_numpy(I).cuda()
-    ih = torch.empty((H, W, B), dtype=torch.uint32, device="cuda")
+    # 8 outputs (315 MB, more than the 256 MB last-level cache) written in turn
+    ihs = [torch.empty((H, W, B), dtype=torch.uint32, device="cuda") for _ in range(8)]
     rd = torch.from_numpy(rects).cuda()
     hs = torch.empty((len(rects), B), dtype=torch.uint32, device="cuda")
-    for _ in range(20):
-        ihb.compute(f, B, out=ih, stream=stream)
-    reps = 400
-    ms = timed(torch, stream, lambda: ihb.compute(f, B, out=ih, stream=stream), reps) / reps
-    qms = timed(torch, stream, lambda: ihb.query_device(ih, rd, out=hs, stream=stream), reps) / reps
+    for k in range(24):
+        ihb.compute(f, B, out=ihs[k % 8], stream=stream)
+    reps = 1000
+    it = iter(range(1 << 30))
+    ms = timed(torch, stream, lambda: ihb.compute(f, B, out=ihs[next(it) % 8], stream=stream), reps) / reps
+    it = iter(range(1 << 30))
+    qms = timed(torch, stream, lambda: ihb.query_device(ihs[next(it) % 8], rd, out=hs, stream=stream),
+                reps) / reps
     out["plain_frame_640x480_B32"] = {"ms_per_frame": ms, "entries_per_s": H * W * B / (ms / 1e3),
-                                      "query_1000_rects_ms": qms}
-    del f, ih, rd, hs
+                                      "hbm_frac": (H * W + 4 * H * W * B) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                      "calls": reps, "rotating_outputs": 8, "query_1000_rects_ms": qms}
+    del f, ihs, rd, hs
     I, B, rects = synth.mixture_frame()
     H, W = I.shape
     f = torch.from_numpy(I).cuda()
@@ -171,6 +211,37 @@ def plain_and_query_legs(torch, ihb, synth, stream) -> dict:
     del f, ih, rd, hs
     torch.cuda.empty_cache()
     return out
+
+
+def transfer_leg(torch, ihb) -> dict:
+    """The host-transfer pipeline (frames uploaded, whole integral histograms
+    downloaded to pinned host memory, copies and kernels of consecutive frames
+    on 1 or 2 streams): frames/s including the PCIe copies, the figure the
+    paper reports.  Frames: uniform pixels from seed 6.  Each case checks one
+    output row against the oracle."""
+    import oracle
+    orc = oracle.get()
+    rng = np.random.default_rng(6)
+    res = {}
+    for (H, W, B, n) in ((480, 640, 32, 100), (720, 1280, 16, 50), (720, 1280, 128, 12)):
+        frames = [torch.from_numpy(rng.integers(0, 256, size=(H, W), dtype=np.uint8)).pin_memory()
+                  for _ in range(n)]
+        outs = [torch.empty((H, W, B), dtype=torch.uint32).pin_memory() for _ in range(n)]
+        case = {}
+        for ns in (1, 2):
+            ihb.transfer_pipeline(frames[:2], outs[:2], B, n_streams=ns)      # warm-up
+            st = ihb.transfer_pipeline(frames, outs, B, n_streams=ns)
+            case[f"streams_{ns}"] = {"frames_per_s": st["frames_per_s"], "wall_ms": st["wall_ms"],
+                                     "kernel_ms_per_frame": st["kernel_ms"] / n,
+                                     "d2h_ms_per_frame": st["d2h_ms"] / n,
+                                     "d2h_gbs": H * W * B * 4 * n / (st["d2h_ms"] / 1e3) / 1e9}
+        k = n - 1
+        assert np.array_equal(outs[k][H - 1].numpy(), orc.row_by_definition(frames[k].numpy(), B, H - 1)), \
+            f"transfer pipeline parity spot check failed ({H}x{W} B={B})"
+        case["dual_buffer_gain"] = case["streams_2"]["frames_per_s"] / case["streams_1"]["frames_per_s"]
+        res[f"{W}x{H}_B{B}_{n}_frames"] = case
+        del frames, outs
+    return res
 
 
 def uneven_leg(torch, ihb, synth, stream) -> dict:
@@ -387,6 +458,9 @@ def main():
     if not args.no_uneven:
         legs["uneven_batch_256"] = uneven_leg(torch, ihb, synth, stream)
         log(f"[bench] uneven batch: {legs['uneven_batch_256']}")
+    if not args.no_transfer:
+        legs["transfer_pipeline"] = transfer_leg(torch, ihb)
+        log(f"[bench] transfer pipeline: {legs['transfer_pipeline']}")
     served = None
     torch.cuda.empty_cache()
     if args.serve_seconds > 0:

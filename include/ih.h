@@ -182,6 +182,38 @@ ih_status ih_batch_plan_frame_tile(const ih_batch_plan* plan, size_t k, int32_t*
                                    int32_t* tile_y, int32_t* nontemporal);
 
 /* ---------------------------------------------------------------------------
+ * Host-transfer pipeline (Sec. 4.4, Algorithm 6): frames in host memory, whole
+ * integral histograms back to host memory, copies and kernels of consecutive
+ * frames overlapped on several streams.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    double wall_ms;        /* earliest upload start to latest download end        */
+    double frames_per_s;   /* frames / wall                                        */
+    double h2d_ms;         /* per-stage sums over frames, each stage timed on its  */
+    double kernel_ms;      /* own stream (a stage that waits for the device to     */
+    double d2h_ms;         /* free up counts the wait)                             */
+} ih_pipeline_stats;
+
+/*
+ * ih_transfer_pipeline -- for k in [0, n): upload frames_host[k] (H*W uint8),
+ * compute its integral histogram (Sec. 2.1 Eq. 1; same kernels and tile as
+ * ih_compute) and download all H*W*B uint32 of it to outs_host[k].  Frame k
+ * runs on stream k mod n_streams (n_streams in [1, 8]; 2 is the paper's double
+ * buffering), each stream with its own device buffers, so one frame's download
+ * overlaps the next frames' uploads and kernels.  Host buffers are the
+ * caller's; pinned ones (hipHostMalloc) move at full link speed, pageable ones
+ * are staged by the runtime.  Output buffers must not alias.  Blocking: returns
+ * when every output is in host memory; device buffers are allocated and freed
+ * by the call.  stats may be NULL (then no events are recorded).
+ * Errors: IH_ERR_INVALID_ARG (null pointer, n == 0, bad shape or n_streams),
+ * IH_ERR_RANGE, IH_ERR_OOM, IH_ERR_HIP.
+ */
+ih_status ih_transfer_pipeline(const uint8_t* const* frames_host, uint32_t* const* outs_host, size_t n,
+                               int32_t H, int32_t W, int32_t B, int32_t n_streams,
+                               ih_pipeline_stats* stats);
+
+/* ---------------------------------------------------------------------------
  * Served form: frame + region-query requests from many video streams.
  * ------------------------------------------------------------------------- */
 

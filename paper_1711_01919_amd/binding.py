@@ -76,6 +76,11 @@ class ServerCounters(ctypes.Structure):
                 ("budget_blocked", ctypes.c_uint64)]
 
 
+class PipelineStats(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double), ("h2d_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("d2h_ms", ctypes.c_double)]
+
+
 def _load() -> ctypes.CDLL:
     if not LIB_PATH.exists():
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1711_01919_amd.build`")
@@ -110,6 +115,9 @@ def _load() -> ctypes.CDLL:
     for f in (lib.ih_server_create, lib.ih_submit, lib.ih_poll, lib.ih_server_query_latest,
               lib.ih_server_stats, lib.ih_server_destroy, lib.ih_server_hold):
         f.restype = ctypes.c_int
+    lib.ih_transfer_pipeline.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), sz, i32, i32, i32, i32,
+                                         ctypes.POINTER(PipelineStats)]
+    lib.ih_transfer_pipeline.restype = ctypes.c_int
     lib.ih_status_str.argtypes = [ctypes.c_int]
     lib.ih_status_str.restype = ctypes.c_char_p
     lib.ih_last_error.restype = ctypes.c_char_p
@@ -327,6 +335,40 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _host_ptr(a) -> int:
+    """Address of a C-contiguous host buffer (numpy array or CPU tensor)."""
+    if isinstance(a, torch.Tensor):
+        if a.is_cuda or not a.is_contiguous():
+            raise ValueError("host buffers must be contiguous CPU tensors")
+        return a.data_ptr()
+    if not (isinstance(a, np.ndarray) and a.flags.c_contiguous):
+        raise ValueError("host buffers must be C-contiguous numpy arrays or CPU tensors")
+    return a.ctypes.data
+
+
+def transfer_pipeline(frames, outs, B: int, n_streams: int = 2) -> dict:
+    """ih_transfer_pipeline: host frames (H x W uint8 each, one shape) to host
+    integral histograms (H x W x B uint32 each), copies and kernels of
+    consecutive frames overlapped on n_streams streams.  Returns the timing."""
+    if len(frames) == 0 or len(frames) != len(outs):
+        raise ValueError("frames and outs must be equally long and non-empty")
+    H, W = frames[0].shape
+    for f, o in zip(frames, outs):
+        if tuple(f.shape) != (H, W) or f.dtype not in (np.uint8, torch.uint8):
+            raise ValueError(f"every frame must be a {H}x{W} uint8 array")
+        n_el = o.numel() if isinstance(o, torch.Tensor) else o.size
+        if o.dtype not in (np.uint32, torch.uint32) or n_el < H * W * B:
+            raise ValueError("every output must be a uint32 buffer of H*W*B elements")
+    n = len(frames)
+    fp = (ctypes.c_void_p * n)(*[_host_ptr(f) for f in frames])
+    op = (ctypes.c_void_p * n)(*[_host_ptr(o) for o in outs])
+    st = PipelineStats()
+    _check(lib.ih_transfer_pipeline(fp, op, n, H, W, int(B), int(n_streams), ctypes.byref(st)),
+           "ih_transfer_pipeline")
+    return {"wall_ms": st.wall_ms, "frames_per_s": st.frames_per_s, "h2d_ms": st.h2d_ms,
+            "kernel_ms": st.kernel_ms, "d2h_ms": st.d2h_ms}
 
 
 def profile_enable(on: bool = True):

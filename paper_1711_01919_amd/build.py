@@ -38,6 +38,7 @@ SOURCES = {
     "ih_util.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_launch.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_server.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_pipeline.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
 }
 
 

@@ -650,9 +650,15 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B)
     t.nontemporal = false;
     // Tallest tile (fewest carries) that still gives enough independent waves.
     const Geom g0 = make_geom(H, W, B, TileChoice{t.TX, 1, false});
-    int TY = 256;
+    int TY = 512;
     while (TY > 16 && (int64_t)((H + TY - 1) / TY) * g0.nJG < 2048) TY /= 2;
     t.TY = TY;
+    // Small frames (under 1024 waves even at 16 rows): narrower and shorter
+    // tiles for parallelism; their carries stay in cache.
+    if ((int64_t)((H + TY - 1) / TY) * g0.nJG < 1024) {
+        t.TX = 32;
+        t.TY = 8;
+    }
     return t;
 }
 

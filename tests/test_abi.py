@@ -73,3 +73,23 @@ def test_query_rejects_bad_rectangles_before_launch(lib):
         assert f(ctypes.byref(v), ctypes.addressof(rects), 2, 0x2000) == 1
     assert f(None, None, 1, 0x2000) == 1
     assert f(ctypes.byref(v), None, 0, None) == 0              # n = 0 is a no-op
+
+
+def test_transfer_pipeline_rejects_bad_arguments_before_launch(lib):
+    f = lib.ih_transfer_pipeline
+    vp = ctypes.c_void_p
+    f.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_int32, ctypes.c_int32, vp]
+    fake = 0x1000  # never dereferenced: validation fails first
+    one = (vp * 1)(fake)
+    null_entry = (vp * 2)(fake, None)
+    two = (vp * 2)(fake, fake)
+    assert f(None, one, 1, 4, 4, 8, 2, None) == 1
+    assert f(one, None, 1, 4, 4, 8, 2, None) == 1
+    assert f(one, one, 0, 4, 4, 8, 2, None) == 1               # no frames
+    assert f(one, one, 1, 4, 4, 8, 0, None) == 1               # n_streams out of range
+    assert f(one, one, 1, 4, 4, 8, 9, None) == 1
+    assert f(one, one, 1, 0, 4, 8, 2, None) == 1               # bad shape
+    assert f(one, one, 1, 4, 4, 300, 2, None) == 1
+    assert f(one, one, 1, 65536, 65536, 8, 2, None) == 2       # H*W = 2^32
+    assert f(two, null_entry, 2, 4, 4, 8, 2, None) == 1        # null output pointer
