@@ -39,6 +39,7 @@ SOURCES = {
     "ih_launch.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_server.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_pipeline.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_geom.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
 }
 
 

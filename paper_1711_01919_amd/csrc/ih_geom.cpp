@@ -1,0 +1,108 @@
+// Host-side geometry of the tile decomposition: scratch layout, frame
+// arguments, supported tiles and the single-frame tile heuristic, and the
+// choice of compiled tile-kernel variant.  No device code.
+#include "ih_internal.h"
+
+namespace ih {
+
+ScratchLayout scratch_layout(const Geom& g)
+{
+    ScratchLayout s;
+    s.rowc = 0;
+    s.colc = s.rowc + (size_t)g.H * g.nTX * g.B;
+    s.corner = s.colc + (size_t)g.nTY * g.W * g.B;
+    s.words = s.corner + (size_t)g.nTY * g.nTX * g.B;
+    return s;
+}
+
+FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g)
+{
+    const ScratchLayout sl = scratch_layout(g);
+    return FrameArgs{frame, out, scratch + sl.rowc, scratch + sl.colc, scratch + sl.corner, g};
+}
+
+int bins_per_lane(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
+
+Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t)
+{
+    Geom g;
+    g.H = H; g.W = W; g.B = B;
+    g.TX = t.TX; g.TY = t.TY;
+    g.nTX = (W + t.TX - 1) / t.TX;
+    g.nTY = (H + t.TY - 1) / t.TY;
+    g.BPL = bins_per_lane(B);
+    g.L = (B + g.BPL - 1) / g.BPL;
+    g.S = kWave / g.L;
+    g.nJG = (g.nTX + g.S - 1) / g.S;
+    return g;
+}
+
+bool tile_supported(int32_t B, const TileChoice& t)
+{
+    const int bpl = bins_per_lane(B);
+    if (t.TY < 1 || t.TY > 65535) return false;
+    if (bpl == 4) return t.TX == 32;
+    if (bpl == 2) return t.TX == 32 || t.TX == 64;
+    // 128 columns of accumulators fit the register file only with one
+    // segment per wave and compile-time B
+    return t.TX == 32 || t.TX == 64 || (t.TX == 128 && B == 64);
+}
+
+TileChoice default_tile(int32_t H, int32_t W, int32_t B)
+{
+    TileChoice t;
+    t.TX = bins_per_lane(B) == 4 ? 32 : 64;
+    t.nontemporal = false;
+    // Tallest tile (fewest carries) that still gives enough independent waves.
+    const Geom g0 = make_geom(H, W, B, TileChoice{t.TX, 1, false});
+    int TY = 512;
+    while (TY > 16 && (int64_t)((H + TY - 1) / TY) * g0.nJG < 2048) TY /= 2;
+    t.TY = TY;
+    // Small frames (under 1024 waves even at 16 rows): narrower and shorter
+    // tiles for parallelism; their carries stay in cache.
+    if ((int64_t)((H + TY - 1) / TY) * g0.nJG < 1024) {
+        t.TX = 32;
+        t.TY = 8;
+    }
+    return t;
+}
+
+int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out)
+{
+    const bool aligned = ((reinterpret_cast<uintptr_t>(frame) & 15) == 0) && (g.W % 16 == 0) &&
+                         (g.B % g.BPL == 0) &&
+                         ((reinterpret_cast<uintptr_t>(out) & (4 * g.BPL - 1)) == 0);
+    if (!aligned) return 0;
+    const int32_t full_tiles = g.W / g.TX;
+    if (full_tiles == g.nTX) return g.nJG;
+    return full_tiles / g.S;
+}
+
+bool TileVariant::operator<(const TileVariant& o) const
+{
+    if (bpl != o.bpl) return bpl < o.bpl;
+    if (tx != o.tx) return tx < o.tx;
+    if (bc != o.bc) return bc < o.bc;
+    if (nt != o.nt) return nt < o.nt;
+    return guard < o.guard;
+}
+bool TileVariant::operator==(const TileVariant& o) const
+{
+    return bpl == o.bpl && tx == o.tx && bc == o.bc && nt == o.nt && guard == o.guard;
+}
+
+// Bin counts with a specialised kernel (compile-time B); others use runtime B.
+static int32_t const_bins(int bpl, int B)
+{
+    if (bpl == 1 && (B == 16 || B == 32 || B == 64)) return B;
+    if (bpl == 2 && B == 128) return B;
+    if (bpl == 4 && B == 256) return B;
+    return 0;
+}
+
+TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard)
+{
+    return TileVariant{g.BPL, g.TX, const_bins(g.BPL, g.B), nontemporal, guard};
+}
+
+}  // namespace ih

@@ -25,7 +25,8 @@ struct Geom {
 };
 
 // Scratch layout (uint32 words) for one frame:
-//   rowc   [H][nTX][B]    left carries: pixels of row y left of segment j, per bin
+//   rowc   [nTX][H][B]    left carries: pixels of row y left of segment j, per bin
+//                         (segment-major, so a tile's rows are one contiguous run)
 //   colc   [nTY][W][B]    column counts per tile band, scanned to top carries
 //   corner [nTY][nTX][B]  per-tile totals, scanned to top-left corner counts
 struct ScratchLayout {

@@ -87,7 +87,7 @@ __device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs,
 // One wave per frame row.  For a chunk of up to kSegChunk tile segments the
 // wave bins the row's pixels into per-segment histograms in LDS (8-bit
 // counters: a segment holds at most TX <= 128 pixels), then each lane walks
-// the segments for its bins and stores the exclusive running count: rowc[y][j][b]
+// the segments for its bins and stores the exclusive running count: rowc[j][y][b]
 // = pixels of row y left of segment j in bin b.
 constexpr int kSegChunk = 64;
 constexpr int kRowThreads = kWave;     // one row per workgroup
@@ -108,7 +108,9 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
     const int lane = threadIdx.x;
     uint32_t run[4] = {0u, 0u, 0u, 0u};
     const IH_GLOBAL uint8_t* prow = gmem(f.frame) + y * g.W;
-    IH_GLOBAL uint32_t* out = gmem(f.rowc) + y * g.nTX * B;
+    // rowc is segment-major, [j][y][b]: a tile wave's rows are contiguous
+    IH_GLOBAL uint32_t* out = gmem(f.rowc) + y * B;
+    const size_t seg_stride = (size_t)g.H * B;
     // 16-byte chunks never straddle a segment (TX is a multiple of 16)
     const bool vec = ((reinterpret_cast<uintptr_t>(prow) & 15) == 0);
     for (int j0 = 0; j0 < g.nTX; j0 += kSegChunk) {
@@ -152,7 +154,7 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
         }
         __syncthreads();
         for (int s = 0; s < ns; ++s) {
-            IH_GLOBAL uint32_t* o = out + (size_t)(j0 + s) * B;
+            IH_GLOBAL uint32_t* o = out + (size_t)(j0 + s) * seg_stride;
             for (int t = 0; t < bpl; ++t) {
                 const int b = lane * bpl + t;
                 if (b < B) {
@@ -368,17 +370,10 @@ __device__ __forceinline__ void store_bins(IH_GLOBAL uint32_t* p, const uint32_t
     }
 }
 
-// Pixels of row y of a tile segment (TX bytes, packed four per dword) and the
-// segment's left carries for that row (pixels of row y left of the segment,
-// per bin).
-template <int BPL, int TX, bool GUARD, bool UNIFORM>
-__device__ __forceinline__ void load_row(const FrameArgs& f, int y, int j, int x0, int b0, int B,
-                                         int ncols, const bool (&bvalid)[BPL],
-                                         uint32_t (&px)[TX / 4], uint32_t (&cnt)[BPL])
+// Pixels of row y of a tile segment (TX bytes, packed four per dword).
+template <int TX, bool GUARD, bool UNIFORM>
+__device__ __forceinline__ void load_px(const FrameArgs& f, int y, int x0, int ncols, uint32_t (&px)[TX / 4])
 {
-    const IH_GLOBAL uint32_t* rp = gmem(f.rowc) + ((size_t)y * f.g.nTX + j) * B + b0;
-#pragma unroll
-    for (int t = 0; t < BPL; ++t) cnt[t] = bvalid[t] ? rp[t] : 0u;
     const IH_GLOBAL uint8_t* prow = gmem(f.frame) + (size_t)y * f.g.W + x0;
     if constexpr (!GUARD && UNIFORM) {
         // One segment per wave: every lane reads the same pixels, so read
@@ -403,6 +398,22 @@ __device__ __forceinline__ void load_row(const FrameArgs& f, int y, int j, int x
 #pragma unroll
         for (int k = 0; k < TX; ++k)
             if (k < ncols) px[k / 4] |= (uint32_t)prow[k] << (8 * (k % 4));
+    }
+}
+
+// Left carries of CH consecutive rows y, y+1, ... of segment j (rows past the
+// band clamped to its last row): CH x B contiguous uint32 in the segment-major
+// rowc, read as one burst.
+template <int BPL, int CH>
+__device__ __forceinline__ void load_carries(const FrameArgs& f, int y, int y_last, int j, int b0, int B,
+                                             const bool (&bvalid)[BPL], uint32_t (&cb)[CH][BPL])
+{
+    const IH_GLOBAL uint32_t* rp = gmem(f.rowc) + (size_t)j * f.g.H * B + b0;
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const IH_GLOBAL uint32_t* r = rp + (size_t)min(y + q, y_last) * B;
+#pragma unroll
+        for (int t = 0; t < BPL; ++t) cb[q][t] = bvalid[t] ? r[t] : 0u;
     }
 }
 
@@ -465,14 +476,11 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
     const bool vec_ok = (b0 + BPL <= B) && (B % BPL == 0) &&
                         ((reinterpret_cast<uintptr_t>(f.out) & (4 * BPL - 1)) == 0);
 
-    // The loads of row y+1 (pixels and left carries) are issued before the
-    // stores of row y: loads and stores share one in-order completion counter
-    // on this architecture, so waiting for a load issued after a row's stores
-    // would also wait for all of those stores to drain.  Two register sets
-    // alternate (no copies), and the prefetch row is clamped into the band so
-    // every wave runs the same control flow.
-    auto row_pass = [&](int y, const uint32_t (&px)[TX / 4], uint32_t (&cnt)[BPL]) {
+    auto row_pass = [&](int y, const uint32_t (&px)[TX / 4], const uint32_t (&c0)[BPL]) {
         IH_GLOBAL uint32_t* orow = gmem(f.out) + ((size_t)y * g.W + x0) * B + b0;
+        uint32_t cnt[BPL];
+#pragma unroll
+        for (int t = 0; t < BPL; ++t) cnt[t] = c0[t];
 #pragma unroll
         for (int k = 0; k < TX; ++k) {
             const uint32_t v = (px[k / 4] >> (8 * (k % 4))) & 0xFFu;
@@ -496,19 +504,46 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
             }
         }
     };
-    uint32_t pxa[TX / 4], cnta[BPL], pxb[TX / 4], cntb[BPL];
-    load_row<BPL, TX, GUARD, UNIFORM>(f, y0, j, x0, b0, B, ncols, bvalid, pxa, cnta);
+    // Reads beside the write stream cost DRAM time per read burst, so the
+    // left carries come CH rows at a time (one contiguous burst from the
+    // segment-major rowc), loaded a chunk ahead into nb and handed to cb,
+    // which shifts down one row per row.  Pixels of row y+1 are loaded before
+    // the stores of row y (two register sets alternate): loads and stores
+    // share one in-order completion counter on this architecture, so a load
+    // issued after a row's stores could only be waited for behind them.
+    // Rows past the band are clamped, so every wave runs the same control flow.
+    constexpr int CH = 8 / BPL;
+    uint32_t cb[CH][BPL], nb[CH][BPL];
+    uint32_t pxa[TX / 4], pxb[TX / 4];
+    load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
+    load_px<TX, GUARD, UNIFORM>(f, y0, x0, ncols, pxa);
     // Drain everything once per work item, so that inside the loop the
     // compiler's counter bookkeeping sees only the in-loop prefetches.
     __builtin_amdgcn_s_waitcnt(0);
-    for (int y = y0; y < y1; y += 2) {
-        load_row<BPL, TX, GUARD, UNIFORM>(f, min(y + 1, y1 - 1), j, x0, b0, B, ncols, bvalid, pxb, cntb);
-        __builtin_amdgcn_sched_barrier(0);        // keep the prefetch ahead of the stores
-        row_pass(y, pxa, cnta);
-        if (y + 1 >= y1) break;
-        load_row<BPL, TX, GUARD, UNIFORM>(f, min(y + 2, y1 - 1), j, x0, b0, B, ncols, bvalid, pxa, cnta);
-        __builtin_amdgcn_sched_barrier(0);
-        row_pass(y + 1, pxb, cntb);
+    for (int yc = y0; yc < y1; yc += CH) {
+        if (yc + CH < y1) load_carries<BPL, CH>(f, yc + CH, y1 - 1, j, b0, B, bvalid, nb);
+#pragma unroll 1
+        for (int r = 0; r < CH; r += 2) {
+            const int y = yc + r;
+            load_px<TX, GUARD, UNIFORM>(f, min(y + 1, y1 - 1), x0, ncols, pxb);
+            __builtin_amdgcn_sched_barrier(0);        // keep the prefetch ahead of the stores
+            if (y < y1) row_pass(y, pxa, cb[0]);
+#pragma unroll
+            for (int q = 0; q + 1 < CH; ++q)
+#pragma unroll
+                for (int t = 0; t < BPL; ++t) cb[q][t] = cb[q + 1][t];
+            load_px<TX, GUARD, UNIFORM>(f, min(y + 2, y1 - 1), x0, ncols, pxa);
+            __builtin_amdgcn_sched_barrier(0);
+            if (y + 1 < y1) row_pass(y + 1, pxb, cb[0]);
+#pragma unroll
+            for (int q = 0; q + 1 < CH; ++q)
+#pragma unroll
+                for (int t = 0; t < BPL; ++t) cb[q][t] = cb[q + 1][t];
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+#pragma unroll
+            for (int t = 0; t < BPL; ++t) cb[q][t] = nb[q][t];
     }
 }
 
@@ -598,108 +633,9 @@ void query_kernel(const uint32_t* __restrict__ ih_, int32_t H, int32_t W, int32_
 }
 
 // ---------------------------------------------------------------------------
-// host side: geometry, variants, launches
+// host side: kernel table and launches (geometry and tile choice live in
+// ih_geom.cpp)
 // ---------------------------------------------------------------------------
-ScratchLayout scratch_layout(const Geom& g)
-{
-    ScratchLayout s;
-    s.rowc = 0;
-    s.colc = s.rowc + (size_t)g.H * g.nTX * g.B;
-    s.corner = s.colc + (size_t)g.nTY * g.W * g.B;
-    s.words = s.corner + (size_t)g.nTY * g.nTX * g.B;
-    return s;
-}
-
-FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g)
-{
-    const ScratchLayout sl = scratch_layout(g);
-    return FrameArgs{frame, out, scratch + sl.rowc, scratch + sl.colc, scratch + sl.corner, g};
-}
-
-int bins_per_lane(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
-
-Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t)
-{
-    Geom g;
-    g.H = H; g.W = W; g.B = B;
-    g.TX = t.TX; g.TY = t.TY;
-    g.nTX = (W + t.TX - 1) / t.TX;
-    g.nTY = (H + t.TY - 1) / t.TY;
-    g.BPL = bins_per_lane(B);
-    g.L = (B + g.BPL - 1) / g.BPL;
-    g.S = kWave / g.L;
-    g.nJG = (g.nTX + g.S - 1) / g.S;
-    return g;
-}
-
-bool tile_supported(int32_t B, const TileChoice& t)
-{
-    const int bpl = bins_per_lane(B);
-    if (t.TY < 1 || t.TY > 65535) return false;
-    if (bpl == 4) return t.TX == 32;
-    if (bpl == 2) return t.TX == 32 || t.TX == 64;
-    // 128 columns of accumulators fit the register file only with one
-    // segment per wave and compile-time B
-    return t.TX == 32 || t.TX == 64 || (t.TX == 128 && B == 64);
-}
-
-TileChoice default_tile(int32_t H, int32_t W, int32_t B)
-{
-    TileChoice t;
-    t.TX = bins_per_lane(B) == 4 ? 32 : 64;
-    t.nontemporal = false;
-    // Tallest tile (fewest carries) that still gives enough independent waves.
-    const Geom g0 = make_geom(H, W, B, TileChoice{t.TX, 1, false});
-    int TY = 512;
-    while (TY > 16 && (int64_t)((H + TY - 1) / TY) * g0.nJG < 2048) TY /= 2;
-    t.TY = TY;
-    // Small frames (under 1024 waves even at 16 rows): narrower and shorter
-    // tiles for parallelism; their carries stay in cache.
-    if ((int64_t)((H + TY - 1) / TY) * g0.nJG < 1024) {
-        t.TX = 32;
-        t.TY = 8;
-    }
-    return t;
-}
-
-int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out)
-{
-    const bool aligned = ((reinterpret_cast<uintptr_t>(frame) & 15) == 0) && (g.W % 16 == 0) &&
-                         (g.B % g.BPL == 0) &&
-                         ((reinterpret_cast<uintptr_t>(out) & (4 * g.BPL - 1)) == 0);
-    if (!aligned) return 0;
-    const int32_t full_tiles = g.W / g.TX;
-    if (full_tiles == g.nTX) return g.nJG;
-    return full_tiles / g.S;
-}
-
-bool TileVariant::operator<(const TileVariant& o) const
-{
-    if (bpl != o.bpl) return bpl < o.bpl;
-    if (tx != o.tx) return tx < o.tx;
-    if (bc != o.bc) return bc < o.bc;
-    if (nt != o.nt) return nt < o.nt;
-    return guard < o.guard;
-}
-bool TileVariant::operator==(const TileVariant& o) const
-{
-    return bpl == o.bpl && tx == o.tx && bc == o.bc && nt == o.nt && guard == o.guard;
-}
-
-// Bin counts with a specialised kernel (compile-time B); others use runtime B.
-static int32_t const_bins(int bpl, int B)
-{
-    if (bpl == 1 && (B == 16 || B == 32 || B == 64)) return B;
-    if (bpl == 2 && B == 128) return B;
-    if (bpl == 4 && B == 256) return B;
-    return 0;
-}
-
-TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard)
-{
-    return TileVariant{g.BPL, g.TX, const_bins(g.BPL, g.B), nontemporal, guard};
-}
-
 // Table of compiled tile kernels: single-frame and batched entry per variant.
 struct TileFns {
     const void* single;
