@@ -40,9 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # reads on the same counters).  Valid only for the kernel source and tile they
 # were taken with; any other combination reports null.
 TRAFFIC_RECORD = {
-    "kernel_src_sha256": "886f746434039841b6ec3696ade4bf7963bed2f11dcc823dfc354d53fa78b69b",
-    "workload": "disc_sequence_64x1080x1920_B64", "tile": [128, 128], "nontemporal": False,
-    "fetch_bytes": 399970.3 * 2.0 * 1024, "write_bytes": 33177600.0 * 1.0 * 1024,
+    "kernel_src_sha256": "786d007de250cfb1fac580ed8cb9b58e7d88a5b7896643d24c27c3e8cc7164c3",
+    "workload": "disc_sequence_64x1080x1920_B64", "tile": [128, 256], "nontemporal": False,
+    "fetch_bytes": 336998.5 * 2.0 * 1024, "write_bytes": 33177600.0 * 1.0 * 1024,
 }
 
 
@@ -211,6 +211,21 @@ def plain_and_query_legs(torch, ihb, synth, stream) -> dict:
     del f, ih, rd, hs
     torch.cuda.empty_cache()
     return out
+
+
+def device_reference(torch) -> dict:
+    """What plain device writes reach on this GPU: torch's fill of 8 GiB and
+    of 32 GiB (write-only streams).  Boxes of the same model differ by tens
+    of percent, so the integral-histogram figures are best read next to these."""
+    res = {}
+    for gib in (8, 32):
+        x = torch.empty(gib << 30, dtype=torch.uint8, device="cuda")
+        x.fill_(1)
+        ms = timed(torch, torch.cuda.current_stream(), lambda: x.fill_(7), 5) / 5
+        res[f"fill_{gib}GiB_gbs"] = (gib << 30) / (ms / 1e3) / 1e9
+        del x
+        torch.cuda.empty_cache()
+    return res
 
 
 def transfer_leg(torch, ihb) -> dict:
@@ -463,6 +478,8 @@ def main():
         log(f"[bench] transfer pipeline: {legs['transfer_pipeline']}")
     served = None
     torch.cuda.empty_cache()
+    legs["device_reference"] = device_reference(torch)
+    log(f"[bench] device reference: {legs['device_reference']}")
     if args.serve_seconds > 0:
         served = serving_leg(torch, ihb, synth, args.serve_seconds)
         log(f"[bench] serving: {served}")

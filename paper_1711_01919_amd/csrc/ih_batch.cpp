@@ -293,7 +293,7 @@ std::vector<ih::TileChoice> candidates(int32_t B)
 // left-carry reads per stored byte) when a band of at least 32 rows still
 // gives that many waves; otherwise the single-frame tile width.
 ih::TileChoice batch_default_tile(const std::vector<ih_frame_desc>& descs, int32_t B,
-                                  int64_t kMinWaves = 8192)
+                                  int64_t kMinWaves = 4096)
 {
     auto waves_of = [&](int tx, int ty) {
         int64_t w = 0;
@@ -431,7 +431,7 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
         // 256-CU device) for its tile pass, so bands stay tall and the two
         // live groups' carries small; non-temporal stores so the output
         // stream leaves the carries in cache.
-        const int64_t min_waves = ng > 1 ? 1792 * ng : 8192;
+        const int64_t min_waves = ng > 1 ? 1792 * ng : 4096;
         for (auto& kv : by_b) {
             choice[kv.first] = batch_default_tile(kv.second, kv.first, min_waves);
             choice[kv.first].nontemporal = ng > 1;
