@@ -275,14 +275,17 @@ void save_cache(TuneCache& c)
             << ' ' << kv.second.TY << ' ' << (kv.second.nontemporal ? 1 : 0) << '\n';
 }
 
-std::vector<ih::TileChoice> candidates(int32_t B)
+std::vector<ih::TileChoice> candidates(int32_t H, int32_t B)
 {
     std::vector<ih::TileChoice> c;
     for (int tx : {32, 64, 128})
         for (int ty : {16, 32, 64, 128, 256})
             for (bool nt : {false, true}) {
-                ih::TileChoice t{tx, ty, nt};
-                if (ih::tile_supported(B, t)) c.push_back(t);
+                ih::TileChoice t{tx, ih::even_band_height(H, ty), nt};
+                if (!ih::tile_supported(B, t)) continue;
+                bool dup = false;
+                for (const ih::TileChoice& u : c) dup |= u.TX == t.TX && u.TY == t.TY && u.nontemporal == t.nontemporal;
+                if (!dup) c.push_back(t);
             }
     return c;
 }
@@ -310,6 +313,7 @@ ih::TileChoice batch_default_tile(const std::vector<ih_frame_desc>& descs, int32
         t.TY = ty;
         if (waves_of(t.TX, ty) >= kMinWaves) break;
     }
+    t.TY = ih::even_band_height(descs[0].H, t.TY);    // bands of the class's first frame made even
     return t;
 }
 
@@ -371,7 +375,7 @@ ih_status autotune(ih_batch_plan* p, hipStream_t s)
             ih::TileChoice best = batch_default_tile(descs, kv.first.B);
             float best_ms = 1e30f;
             if (ih_status st = time_candidate(descs, best, s, &best_ms)) return st;
-            for (const ih::TileChoice& t : candidates(kv.first.B)) {
+            for (const ih::TileChoice& t : candidates(kv.first.H, kv.first.B)) {
                 if (t.TX == best.TX && t.TY == best.TY && t.nontemporal == best.nontemporal) continue;
                 float ms = 0.f;
                 if (ih_status st = time_candidate(descs, t, s, &ms)) return st;

@@ -48,6 +48,12 @@ bool tile_supported(int32_t B, const TileChoice& t)
     return t.TX == 32 || t.TX == 64 || (t.TX == 128 && B == 64);
 }
 
+int32_t even_band_height(int32_t H, int32_t TY)
+{
+    const int32_t n = (H + TY - 1) / TY;
+    return (H + n - 1) / n;
+}
+
 TileChoice default_tile(int32_t H, int32_t W, int32_t B)
 {
     TileChoice t;
@@ -64,6 +70,7 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B)
         t.TX = 32;
         t.TY = 8;
     }
+    t.TY = even_band_height(H, t.TY);
     return t;
 }
 

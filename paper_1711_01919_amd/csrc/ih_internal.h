@@ -65,6 +65,10 @@ struct TileChoice {
 int bins_per_lane(int B);
 Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t);
 TileChoice default_tile(int32_t H, int32_t W, int32_t B);
+// The same number of bands as TY gives, made equally tall (the last band is
+// no shorter than the others by more than one row): a short last band makes
+// short work items that leave the device half idle at the end of a launch.
+int32_t even_band_height(int32_t H, int32_t TY);
 bool tile_supported(int32_t B, const TileChoice& t);
 
 // Column groups [0, n) run the unguarded tile kernel; the rest the guarded one.
