@@ -80,9 +80,9 @@ int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out
                          (g.B % g.BPL == 0) &&
                          ((reinterpret_cast<uintptr_t>(out) & (4 * g.BPL - 1)) == 0);
     if (!aligned) return 0;
-    const int32_t full_tiles = g.W / g.TX;
-    if (full_tiles == g.nTX) return g.nJG;
-    return full_tiles / g.S;
+    // Only groups whose S segments are all whole tiles: the unguarded kernel
+    // may load pixels of every segment of its group.
+    return (g.W / g.TX) / g.S;
 }
 
 bool TileVariant::operator<(const TileVariant& o) const

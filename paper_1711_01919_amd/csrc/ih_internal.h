@@ -71,7 +71,8 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B);
 int32_t even_band_height(int32_t H, int32_t TY);
 bool tile_supported(int32_t B, const TileChoice& t);
 
-// Column groups [0, n) run the unguarded tile kernel; the rest the guarded one.
+// Column groups [0, n) run the unguarded tile kernel; the rest the guarded
+// one.  Unguarded groups hold S whole TX-wide segments, 16-byte aligned.
 int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out);
 
 // Which compiled tile kernel serves a frame part.

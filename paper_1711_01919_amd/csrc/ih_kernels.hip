@@ -418,9 +418,9 @@ __device__ __forceinline__ void load_carries(const FrameArgs& f, int y, int y_la
 }
 
 // One wave, one work item: tile band i (TY rows) x column group jg (S adjacent
-// tile segments).  GUARD=false requires every active segment to be TX columns
-// wide, the frame and W 16-byte aligned, B % BPL == 0 and out aligned to
-// 4*BPL bytes; the host routes everything else to GUARD=true.
+// tile segments).  GUARD=false requires all S segments of the group to exist
+// and be TX columns wide, the frame and W 16-byte aligned, B % BPL == 0 and
+// out aligned to 4*BPL bytes; the host routes everything else to GUARD=true.
 template <int BPL, int TX, int BC, bool NT, bool GUARD>
 __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int lane)
 {
@@ -512,8 +512,61 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
     // share one in-order completion counter on this architecture, so a load
     // issued after a row's stores could only be waited for behind them.
     // Rows past the band are clamped, so every wave runs the same control flow.
-    constexpr int CH = 8 / BPL;
+    // Several segments per wave (B < 64, compile-time B, whole segments):
+    // the pixels of a chunk of rows for all of the wave's segments come in
+    // one wave-wide load too, and each lane fetches its segment's bytes of a
+    // row from the lane holding them (ds_bpermute).  Piece p (16 bytes) of a
+    // chunk is row r, 16-byte column c, segment s with p = (r * PPR + c) * SC
+    // + s, held by lane p.
+    constexpr int SC = kWave / LC;
+    constexpr int PPR = TX / 16;
+    constexpr bool CHUNK_PX = !GUARD && !UNIFORM && BC != 0 && SC * PPR <= kWave;
+    constexpr int CH = CHUNK_PX ? (8 / BPL < kWave / (SC * PPR) ? 8 / BPL : kWave / (SC * PPR)) : 8 / BPL;
     uint32_t cb[CH][BPL], nb[CH][BPL];
+    if constexpr (CHUNK_PX) {
+        static_assert(CH * SC * PPR <= kWave, "a pixel chunk must fit one wave-wide load");
+        auto load_chunk_px = [&](int yc, u32x4& dst) {
+            const int p = lane < CH * SC * PPR ? lane : 0;
+            const int ps = p % SC, pc_ = (p / SC) % PPR, pr = p / (SC * PPR);
+            const int row = min(yc + pr, y1 - 1);
+            const int px0 = (jg * SC + ps) * TX + 16 * pc_;
+            dst = *reinterpret_cast<const IH_GLOBAL u32x4*>(gmem(f.frame) + (size_t)row * g.W + px0);
+        };
+        u32x4 pc, pn;
+        load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
+        load_chunk_px(y0, pc);
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int yc = y0; yc < y1; yc += CH) {
+            const bool more = yc + CH < y1;
+            if (more) {
+                load_carries<BPL, CH>(f, yc + CH, y1 - 1, j, b0, B, bvalid, nb);
+                load_chunk_px(yc + CH, pn);
+            }
+#pragma unroll 1
+            for (int r = 0; r < CH; ++r) {
+                const int y = yc + r;
+                uint32_t px[TX / 4];
+#pragma unroll
+                for (int q = 0; q < TX / 4; ++q) {
+                    const int src = (r * PPR + q / 4) * SC + s;
+                    px[q] = (uint32_t)__builtin_amdgcn_ds_bpermute(src * 4, (int)pc[q % 4]);
+                }
+                if (y < y1) row_pass(y, px, cb[0]);
+#pragma unroll
+                for (int q = 0; q + 1 < CH; ++q)
+#pragma unroll
+                    for (int t = 0; t < BPL; ++t) cb[q][t] = cb[q + 1][t];
+            }
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < CH; ++q)
+#pragma unroll
+                    for (int t = 0; t < BPL; ++t) cb[q][t] = nb[q][t];
+                pc = pn;
+            }
+        }
+        return;
+    }
     uint32_t pxa[TX / 4], pxb[TX / 4];
     load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
     load_px<TX, GUARD, UNIFORM>(f, y0, x0, ncols, pxa);
