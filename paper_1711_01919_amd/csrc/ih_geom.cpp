@@ -59,14 +59,17 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B)
     TileChoice t;
     t.TX = bins_per_lane(B) == 4 ? 32 : 64;
     t.nontemporal = false;
-    // Tallest tile (fewest carries) that still gives enough independent waves.
+    // Tallest tile (fewest carries) that still gives about 1000 independent
+    // waves (one per work item in a single-frame launch): measured best for
+    // 1080p to 8K frames at B = 16 to 64, against both half and twice that.
+    constexpr int64_t kMinWaves = 960;
     const Geom g0 = make_geom(H, W, B, TileChoice{t.TX, 1, false});
     int TY = 512;
-    while (TY > 16 && (int64_t)((H + TY - 1) / TY) * g0.nJG < 2048) TY /= 2;
+    while (TY > 16 && (int64_t)((H + TY - 1) / TY) * g0.nJG < kMinWaves) TY /= 2;
     t.TY = TY;
-    // Small frames (under 1024 waves even at 16 rows): narrower and shorter
+    // Small frames (too few waves even at 16 rows): narrower and shorter
     // tiles for parallelism; their carries stay in cache.
-    if ((int64_t)((H + TY - 1) / TY) * g0.nJG < 1024) {
+    if ((int64_t)((H + TY - 1) / TY) * g0.nJG < kMinWaves) {
         t.TX = 32;
         t.TY = 8;
     }
