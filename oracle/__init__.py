@@ -56,6 +56,8 @@ class Oracle:
         lib.ihref_Q.restype = ctypes.c_uint32
         lib.ihref_integral_histogram.argtypes = [_u8p, _i64, _i64, _i64, _u32p]
         lib.ihref_integral_histogram.restype = ctypes.c_int
+        lib.ihref_integral_histogram_lut.argtypes = [_u8p, _i64, _i64, _i64, _u8p, _u32p]
+        lib.ihref_integral_histogram_lut.restype = ctypes.c_int
         lib.ihref_integral_rows.argtypes = [_u8p, _i64, _i64, _i64, _i64, _i64, _u32p, _u32p]
         lib.ihref_integral_rows.restype = ctypes.c_int
         lib.ihref_row_by_definition.argtypes = [_u8p, _i64, _i64, _i64, _i64, _u32p]
@@ -87,6 +89,19 @@ class Oracle:
         H, W = I.shape
         out = np.empty((H, W, B), dtype=np.uint32)
         rc = self.lib.ihref_integral_histogram(p, H, W, B, out.ctypes.data_as(_u32p))
+        if rc != 0:
+            raise ValueError("bad arguments")
+        return out
+
+    def integral_histogram_lut(self, I, B: int, lut) -> np.ndarray:
+        """Eq. 1 with bin membership from a 256-entry table (bin of value v = lut[v])."""
+        I, p = self._frame(I)
+        H, W = I.shape
+        lut = np.ascontiguousarray(lut, dtype=np.uint8)
+        if lut.shape != (256,):
+            raise ValueError("lut must hold 256 entries")
+        out = np.zeros((H, W, B), dtype=np.uint32)
+        rc = self.lib.ihref_integral_histogram_lut(p, H, W, B, lut.ctypes.data_as(_u8p), out.ctypes.data_as(_u32p))
         if rc != 0:
             raise ValueError("bad arguments")
         return out
@@ -155,8 +170,11 @@ _default = None
 
 
 def get() -> Oracle:
-    """The default (mistake-free) oracle, compiled on first use."""
+    """The default (mistake-free) oracle, compiled on first use and again
+    whenever its source is newer than the built library."""
     global _default
     if _default is None:
+        if not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
+            compile_oracle(LIB)
         _default = Oracle(LIB)
     return _default

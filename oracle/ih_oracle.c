@@ -12,6 +12,10 @@
  *   ihref_Q                   binning function Q of Sec. 2.1 (text of Eq. 1)
  *   ihref_integral_histogram  Eq. 1, evaluated with the sequential recursion
  *                             of Sec. 2.2, Algorithm 1
+ *   ihref_integral_histogram_lut  Eq. 1 / Algorithm 1 with Q given as a table
+ *                             (bins of arbitrary edges: the paper states Q as
+ *                             membership of I(r,c) in bin b without fixing
+ *                             the bins, Sec. 2.1)
  *   ihref_integral_rows       the same recursion continued over a block of
  *                             rows, for frames whose tensor does not fit RAM
  *   ihref_row_by_definition   one row of Eq. 1, summed directly (columns
@@ -98,6 +102,37 @@ int ihref_integral_histogram(const uint8_t* I, int64_t H, int64_t W, int64_t B, 
 #else
                 if (q == (uint32_t)b) h += 1u;
 #endif
+                out[(y * W + x) * B + b] = h;
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * Sec. 2.2, Algorithm 1 again, with the membership test Q(I(x,y), b) of Eq. 1
+ * read from a table: the pixel of value v counts in bin lut[v] (lut holds 256
+ * entries, each below B).  Any table is accepted; tables whose entries never
+ * decrease give bins that are contiguous value ranges with arbitrary edges.
+ * Returns 0 on success, -1 on bad arguments.
+ */
+int ihref_integral_histogram_lut(const uint8_t* I, int64_t H, int64_t W, int64_t B, const uint8_t* lut,
+                                 uint32_t* out)
+{
+    if (!I || !out || !lut || H <= 0 || W <= 0 || B < 1 || B > 256) return -1;
+    for (int v = 0; v < 256; ++v)
+        if ((int64_t)lut[v] >= B) return -1;
+    for (int64_t y = 0; y < H; ++y) {
+        for (int64_t x = 0; x < W; ++x) {
+#if IHREF_MUTANT == 9
+            const uint32_t q = lut[I[y * W + x] ^ 1u];         /* planted: neighbouring table entry */
+#else
+            const uint32_t q = lut[I[y * W + x]];
+#endif
+            for (int64_t b = 0; b < B; ++b) {
+                uint32_t h = at(out, W, B, x - 1, y, b) + at(out, W, B, x, y - 1, b)
+                           - at(out, W, B, x - 1, y - 1, b);
+                if (q == (uint32_t)b) h += 1u;
                 out[(y * W + x) * B + b] = h;
             }
         }

@@ -9,6 +9,8 @@ fix, none of which re-types the oracle's own recursion.
   - the textbook route cumsum(cumsum(one-hot)) on a full 640x480 frame;
   - hand-worked fixtures under tests/golden/;
   - Eq. 2 against direct pixel counting and the area invariant;
+  - table binning: brute force with the table's one-hot, the uniform table
+    equals Q, empty bins stay zero;
   - planted mistakes: every mutant build of the oracle must fail a pin.
 """
 import json
@@ -30,8 +32,21 @@ def onehot_numpy(I, B):
     return ((v * B >= 256 * b) & (v * B < 256 * (b + 1))).astype(np.uint32)
 
 
-def brute_eq1(I, B):
-    oh = onehot_numpy(I, B)
+def onehot_lut_numpy(I, B, lut):
+    """One-hot of a frame binned through a 256-entry table, in numpy."""
+    q = np.asarray(lut, dtype=np.int64)[I.astype(np.int64)]
+    return (q[..., None] == np.arange(B)).astype(np.uint32)
+
+
+def random_monotone_lut(rng, B):
+    """Non-decreasing table over [0, 256) with values in [0, B): bin edges
+    drawn at random, so some bins may be empty."""
+    edges = np.sort(rng.integers(0, 257, size=B - 1))
+    return np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8)
+
+
+def brute_eq1(I, B, oh=None):
+    oh = onehot_numpy(I, B) if oh is None else oh
     H, W = I.shape
     out = np.zeros((H, W, B), dtype=np.uint32)
     for y in range(H):
@@ -153,6 +168,29 @@ def pin_failures(orc, quick=False):
         if orc.entry(I, B, x, y, b) != ref[y, x, b]:
             fails.append(f"entry-{x}-{y}-{b}")
 
+    # table binning (bins with arbitrary edges, and arbitrary tables): brute
+    # force with the table's one-hot, the uniform table equals Q, invariants
+    for (H, W, B) in ((1, 1, 1), (3, 7, 3), (9, 4, 16), (6, 6, 7), (5, 9, 256)):
+        for monotone in (True, False):
+            lut = random_monotone_lut(rng, B) if monotone else rng.integers(0, B, size=256).astype(np.uint8)
+            I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+            got = orc.integral_histogram_lut(I, B, lut)
+            if not np.array_equal(got, brute_eq1(I, B, onehot_lut_numpy(I, B, lut))):
+                fails.append(f"lut-brute-{H}x{W}-B{B}-{monotone}")
+    for B in (2, 5, 64):
+        I = rng.integers(0, 256, size=(17, 23), dtype=np.uint8)
+        qtable = ((np.arange(256) * B) >> 8).astype(np.uint8)
+        if not np.array_equal(orc.integral_histogram_lut(I, B, qtable), brute_eq1(I, B)):
+            fails.append(f"lut-uniform-B{B}")
+    lut = np.zeros(256, np.uint8)
+    lut[200:] = 3                                                  # bins 1, 2 empty
+    I = rng.integers(0, 256, size=(11, 13), dtype=np.uint8)
+    got = orc.integral_histogram_lut(I, 4, lut).astype(np.int64)
+    xy = (np.arange(11)[:, None] + 1) * (np.arange(13)[None, :] + 1)
+    if not (np.array_equal(got.sum(axis=2), xy) and not got[..., 1:3].any()
+            and got[-1, -1, 3] == int((I >= 200).sum())):
+        fails.append("lut-empty-bins")
+
     # Eq. 2 against direct counting in numpy and the area invariant
     for (H, W, B) in ((31, 47, 16), (9, 5, 3), (1, 1, 2), (1, 33, 7), (40, 1, 256)):
         I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
@@ -215,7 +253,7 @@ def test_rejects_bad_arguments(orc):
             orc.region_histogram(IH, np.array([r]))
 
 
-@pytest.mark.parametrize("mutant", range(1, 9))
+@pytest.mark.parametrize("mutant", range(1, 10))
 def test_planted_mistakes_are_caught(tmp_path, mutant):
     """Each planted mistake in the oracle (a rounding binning, a dropped or
     sign-flipped corner term, a lost pixel, an off-by-one corner in Eq. 2, a
