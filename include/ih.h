@@ -82,6 +82,20 @@ ih_status ih_compute(const uint8_t* frame, int32_t H, int32_t W, int32_t B,
                      uint32_t* out, ih_stream_t stream);
 
 /*
+ * ih_compute_lut -- as ih_compute, with the bins given by a table: the pixel
+ * of value v counts in bin lut_host[v].  The paper states the binning only as
+ * membership of a pixel value in a bin (Sec. 2.1, the Q of Eq. 1); a table
+ * gives bins of arbitrary edges.  lut_host: 256 host bytes, each below B and
+ * never decreasing (lut_host[v] <= lut_host[v+1]), so every bin is one range
+ * of values, possibly empty.  The table is copied before the call returns
+ * (the caller may reuse it at once); the kernels are asynchronous on stream.
+ * Errors: as ih_compute, and IH_ERR_INVALID_ARG for a null table, an entry
+ * >= B or a decreasing table (checked before anything is launched).
+ */
+ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, const uint8_t* lut_host,
+                         uint32_t* out, ih_stream_t stream);
+
+/*
  * ih_query -- region histograms by the four-corner rule (Sec. 2.1, Eq. 2):
  *
  *   h(R, b) = H(x1, y1, b) - H(x0-1, y1, b) - H(x1, y0-1, b) + H(x0-1, y0-1, b)

@@ -63,9 +63,9 @@ ih_status get_scratch(hipStream_t stream, size_t bytes, void** out)
 
 // The three phases of one frame on one stream, timed when profiling is on.
 ih_status enqueue_frame(const uint8_t* frame, uint32_t* out, uint32_t* scratch,
-                        const ih::Geom& g, bool nt, hipStream_t s)
+                        const ih::Geom& g, bool nt, hipStream_t s, const uint8_t* lut = nullptr)
 {
-    const ih::FrameArgs fa = ih::frame_args(frame, out, scratch, g);
+    const ih::FrameArgs fa = ih::frame_args(frame, out, scratch, g, lut);
     ih::PhaseTimer timer;
     for (int ph = 0; ph < ih::kNumPhases; ++ph) {
         if (ih_status st = timer.begin(ph, s)) return st;
@@ -119,6 +119,33 @@ ih_status ih_compute(const uint8_t* frame, int32_t H, int32_t W, int32_t B,
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (ih_status st = get_scratch(s, sl.words * sizeof(uint32_t), &scratch)) return st;
     return enqueue_frame(frame, out, static_cast<uint32_t*>(scratch), g, t.nontemporal, s);
+}
+
+ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, const uint8_t* lut_host,
+                         uint32_t* out, ih_stream_t stream)
+{
+    if (!frame || !out || !lut_host) return fail(IH_ERR_INVALID_ARG, "frame, lut and out must be non-null");
+    if (ih_status st = ih::check_shape(H, W, B)) return st;
+    if (reinterpret_cast<uintptr_t>(out) & 3u) return fail(IH_ERR_INVALID_ARG, "out must be 4-byte aligned");
+    for (int v = 0; v < 256; ++v) {
+        if ((int32_t)lut_host[v] >= B)
+            return fail(IH_ERR_INVALID_ARG, "lut[%d]=%d is not a bin below B=%d", v, lut_host[v], B);
+        if (v > 0 && lut_host[v] < lut_host[v - 1])
+            return fail(IH_ERR_INVALID_ARG, "lut decreases at %d (%d after %d)", v, lut_host[v], lut_host[v - 1]);
+    }
+    const ih::TileChoice t = ih::default_tile(H, W, B);
+    const ih::Geom g = ih::make_geom(H, W, B, t);
+    const size_t carry_bytes = (ih::scratch_layout(g).words * sizeof(uint32_t) + 255) / 256 * 256;
+    void* scratch = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ih_status st = get_scratch(s, carry_bytes + 256, &scratch)) return st;
+    uint32_t* dlut = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(scratch) + carry_bytes);
+    // the table goes into this stream's scratch in stream order, after the
+    // kernels of earlier calls that read the previous table
+    hipError_t e = ih::launch_lut_store(lut_host, dlut, s);
+    if (e != hipSuccess) return hip_fail(e, "bin table upload");
+    return enqueue_frame(frame, out, static_cast<uint32_t*>(scratch), g, t.nontemporal, s,
+                         reinterpret_cast<const uint8_t*>(dlut));
 }
 
 ih_status ih_query(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* hists)

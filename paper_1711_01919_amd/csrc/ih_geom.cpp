@@ -15,10 +15,11 @@ ScratchLayout scratch_layout(const Geom& g)
     return s;
 }
 
-FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g)
+FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g,
+                     const uint8_t* lut)
 {
     const ScratchLayout sl = scratch_layout(g);
-    return FrameArgs{frame, out, scratch + sl.rowc, scratch + sl.colc, scratch + sl.corner, g};
+    return FrameArgs{frame, out, scratch + sl.rowc, scratch + sl.colc, scratch + sl.corner, lut, g};
 }
 
 int bins_per_lane(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
@@ -94,11 +95,12 @@ bool TileVariant::operator<(const TileVariant& o) const
     if (tx != o.tx) return tx < o.tx;
     if (bc != o.bc) return bc < o.bc;
     if (nt != o.nt) return nt < o.nt;
-    return guard < o.guard;
+    if (guard != o.guard) return guard < o.guard;
+    return table < o.table;
 }
 bool TileVariant::operator==(const TileVariant& o) const
 {
-    return bpl == o.bpl && tx == o.tx && bc == o.bc && nt == o.nt && guard == o.guard;
+    return bpl == o.bpl && tx == o.tx && bc == o.bc && nt == o.nt && guard == o.guard && table == o.table;
 }
 
 // Bin counts with a specialised kernel (compile-time B); others use runtime B.
@@ -110,9 +112,10 @@ static int32_t const_bins(int bpl, int B)
     return 0;
 }
 
-TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard)
+TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard, bool table)
 {
-    return TileVariant{g.BPL, g.TX, const_bins(g.BPL, g.B), nontemporal, guard};
+    if (table) return TileVariant{g.BPL, g.TX, 0, false, guard, true};
+    return TileVariant{g.BPL, g.TX, const_bins(g.BPL, g.B), nontemporal, guard, false};
 }
 
 }  // namespace ih

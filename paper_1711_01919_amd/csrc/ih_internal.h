@@ -41,9 +41,11 @@ struct FrameArgs {
     uint32_t* rowc;
     uint32_t* colc;
     uint32_t* corner;
+    const uint8_t* lut;      // device bin table (256 entries, non-decreasing, < B); null: floor(v B / 256)
     Geom g;
 };
-FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g);
+FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g,
+                     const uint8_t* lut = nullptr);
 
 // A job maps a contiguous range of a batched launch -- blocks for the count
 // and scan kernels, work items (one per wave) for the tile kernel -- to one
@@ -79,10 +81,11 @@ int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out
 struct TileVariant {
     int32_t bpl, tx, bc;     // bins per lane, tile width, compile-time B (0: runtime B)
     bool nt, guard;
+    bool table;              // bins from a table (runtime B, regular stores, TX <= 64)
     bool operator<(const TileVariant& o) const;
     bool operator==(const TileVariant& o) const;
 };
-TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard);
+TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard, bool table = false);
 
 // ---- single frame: the three phases in order on one stream ----------------
 enum class Phase { kAgg = 0, kScan = 1, kTile = 2 };
@@ -109,6 +112,10 @@ int32_t tile_resident_blocks(const TileVariant& v);
 // Blocks of the scan kernels for one frame.
 int64_t scan_a_blocks(const Geom& g);
 int64_t scan_b_blocks(const Geom& g);
+
+// Copy a host bin table (256 bytes, passed by value as a kernel argument) to
+// device memory dst (64 uint32, 4-byte aligned), in stream order.
+hipError_t launch_lut_store(const uint8_t* lut_host, uint32_t* dst, hipStream_t stream);
 
 // ---- region query ---------------------------------------------------------
 hipError_t launch_query(const uint32_t* ih, int32_t H, int32_t W, int32_t B,

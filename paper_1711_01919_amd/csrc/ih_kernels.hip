@@ -26,6 +26,8 @@
 // sorted job table and run the same body.
 #include "ih_internal.h"
 
+#include <cstring>
+
 namespace ih {
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -101,6 +103,30 @@ __device__ __forceinline__ uint32_t lds_get8(const uint32_t* h, uint32_t e)
     return (h[e >> 2] >> ((e & 3u) << 3)) & 0xFFu;
 }
 
+// Bin of a pixel value.  A frame either uses the uniform bins floor(v B / 256)
+// or a table of 256 bins (non-decreasing, so each bin is one value range),
+// which the count kernels stage in LDS, four entries per word.
+__device__ __forceinline__ void stage_lut(const FrameArgs& f, uint32_t* lutw, int tid, int nthreads)
+{
+    if (f.lut)
+        for (int e = tid; e < 64; e += nthreads) lutw[e] = reinterpret_cast<const IH_GLOBAL uint32_t*>(gmem(f.lut))[e];
+}
+__device__ __forceinline__ uint32_t bin_of(const FrameArgs& f, const uint32_t* lutw, uint32_t v, uint32_t B)
+{
+    return f.lut ? (lutw[v >> 2] >> (8 * (v & 3u))) & 0xFFu : (v * B) >> 8;
+}
+
+// Entries of a non-decreasing 256-entry bin table below bin b, i.e. the first
+// value of bin b (binary search in nine halving steps).
+__device__ __forceinline__ uint32_t lut_count_below(const IH_GLOBAL uint8_t* lut, uint32_t b)
+{
+    uint32_t pos = 0;
+#pragma unroll 1
+    for (uint32_t step = 256; step > 0; step >>= 1)
+        if (pos + step <= 256 && lut[pos + step - 1] < b) pos += step;
+    return pos;
+}
+
 __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uint32_t* lds)
 {
     const Geom& g = f.g;
@@ -113,6 +139,9 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
     const size_t seg_stride = (size_t)g.H * B;
     // 16-byte chunks never straddle a segment (TX is a multiple of 16)
     const bool vec = ((reinterpret_cast<uintptr_t>(prow) & 15) == 0);
+    // the bin table sits after the counters of the largest segment chunk
+    uint32_t* lutw = lds + (((kSegChunk < g.nTX ? kSegChunk : g.nTX) * B + 3) / 4);
+    stage_lut(f, lutw, lane, kRowThreads);      // visible after the first barrier below
     for (int j0 = 0; j0 < g.nTX; j0 += kSegChunk) {
         const int ns = min(kSegChunk, g.nTX - j0);
         for (int w = lane; w < (ns * B + 3) / 4; w += kRowThreads) lds[w] = 0u;
@@ -147,7 +176,7 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
                 for (int k = 0; k < 16; ++k) {
                     if (p + k < npx) {
                         const uint32_t v = (words[k / 4] >> (8 * (k % 4))) & 0xFFu;
-                        lds_inc8(lds, seg + ((v * (uint32_t)B) >> 8));
+                        lds_inc8(lds, seg + bin_of(f, lutw, v, (uint32_t)B));
                     }
                 }
             }
@@ -168,11 +197,11 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
 }
 
 // LDS bytes a row-carry workgroup needs for a frame: 8-bit counters for the
-// segments of one chunk.
+// segments of one chunk, then the 256-entry bin table.
 __host__ __device__ inline size_t rowcarry_lds_bytes(const Geom& g)
 {
     const int ns = g.nTX < kSegChunk ? g.nTX : kSegChunk;
-    return ((size_t)ns * g.B + 3) / 4 * 4;
+    return ((size_t)ns * g.B + 3) / 4 * 4 + 256;
 }
 
 __global__ __launch_bounds__(kRowThreads)
@@ -210,7 +239,7 @@ __device__ __forceinline__ uint32_t lds_get16(const uint32_t* h, uint32_t e)
 }
 
 template <int TX>
-__device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint32_t* colh)
+__device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint32_t* colh, uint32_t* lutw)
 {
     constexpr int kRowsPerPass = kAggThreads / TX;
     const Geom& g = f.g;
@@ -224,6 +253,7 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     const int tr = tid / TX, tx = tid % TX;
 
     for (int e = tid; e < (TX * B + 1) / 2; e += kAggThreads) colh[e] = 0;
+    stage_lut(f, lutw, tid, kAggThreads);
     __syncthreads();
     if (tx < tw) {
         const IH_GLOBAL uint8_t* p = gmem(f.frame) + (size_t)y0 * g.W + x0 + tx;
@@ -238,7 +268,7 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (r0 + u * kRowsPerPass < th)
-                    lds_inc16(colh, (uint32_t)(tx * B) + ((v[u] * (uint32_t)B) >> 8));
+                    lds_inc16(colh, (uint32_t)(tx * B) + bin_of(f, lutw, v[u], (uint32_t)B));
         }
     }
     __syncthreads();
@@ -260,7 +290,8 @@ __global__ __launch_bounds__(kAggThreads)
 void agg_kernel(FrameArgs f)
 {
     __shared__ uint32_t colh[TX * agg_max_bins<TX>() / 2];
-    agg_body<TX>(f, blockIdx.x, colh);
+    __shared__ uint32_t lutw[64];
+    agg_body<TX>(f, blockIdx.x, colh, lutw);
 }
 
 template <int TX>
@@ -268,9 +299,10 @@ __global__ __launch_bounds__(kAggThreads)
 void agg_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
     __shared__ uint32_t colh[TX * agg_max_bins<TX>() / 2];
+    __shared__ uint32_t lutw[64];
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
-    agg_body<TX>(f, (int64_t)blockIdx.x - jb.begin, colh);
+    agg_body<TX>(f, (int64_t)blockIdx.x - jb.begin, colh, lutw);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,7 +453,7 @@ __device__ __forceinline__ void load_carries(const FrameArgs& f, int y, int y_la
 // tile segments).  GUARD=false requires all S segments of the group to exist
 // and be TX columns wide, the frame and W 16-byte aligned, B % BPL == 0 and
 // out aligned to 4*BPL bytes; the host routes everything else to GUARD=true.
-template <int BPL, int TX, int BC, bool NT, bool GUARD>
+template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE>
 __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int lane)
 {
     static_assert(TX % 16 == 0, "pixel rows are loaded 16 bytes at a time");
@@ -441,18 +473,33 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
     const int y0 = i * g.TY;
     const int y1 = min(g.H, y0 + g.TY);
 
-    // Bin b holds the values v with ceil(256 b / B) <= v < ceil(256 (b+1) / B),
-    // which is floor(v B / 256) == b.  A lane tests v - lo < width (unsigned).
+    // Bin b holds the values v in [lo, lo + width).  Uniform bins: v with
+    // ceil(256 b / B) <= v < ceil(256 (b+1) / B), which is floor(v B / 256)
+    // == b.  A bin table: lo = #{v : lut[v] < b}, lo + width = #{v : lut[v]
+    // <= b} (the table never decreases).  A lane tests v - lo < width
+    // (unsigned); an empty bin has width 0.
     uint32_t lo[BPL], wd[BPL];
     bool bvalid[BPL];
 #pragma unroll
-    for (int t = 0; t < BPL; ++t) {
-        const int b = b0 + t;
-        bvalid[t] = GUARD ? b < B : true;
-        const uint32_t l = (uint32_t)(256 * b + B - 1) / (uint32_t)B;
-        const uint32_t h = (uint32_t)(256 * (b + 1) + B - 1) / (uint32_t)B;
-        lo[t] = bvalid[t] ? l : 0u;
-        wd[t] = bvalid[t] ? h - l : 0u;
+    for (int t = 0; t < BPL; ++t) bvalid[t] = GUARD ? b0 + t < B : true;
+    if constexpr (TABLE) {
+        const IH_GLOBAL uint8_t* lt = gmem(f.lut);
+#pragma unroll
+        for (int t = 0; t < BPL; ++t) {
+            const uint32_t l = lut_count_below(lt, (uint32_t)(b0 + t));
+            const uint32_t h = lut_count_below(lt, (uint32_t)(b0 + t + 1));
+            lo[t] = bvalid[t] ? l : 0u;
+            wd[t] = bvalid[t] ? h - l : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < BPL; ++t) {
+            const int b = b0 + t;
+            const uint32_t l = (uint32_t)(256 * b + B - 1) / (uint32_t)B;
+            const uint32_t h = (uint32_t)(256 * (b + 1) + B - 1) / (uint32_t)B;
+            lo[t] = bvalid[t] ? l : 0u;
+            wd[t] = bvalid[t] ? h - l : 0u;
+        }
     }
 
     // Column state: corner + running sum of the top carries along the segment.
@@ -600,7 +647,7 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
     }
 }
 
-template <int BPL, int TX, int BC, bool NT, bool GUARD>
+template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE>
 __global__ __launch_bounds__(kWave * kWavesPerBlock)
 void tile_kernel(FrameArgs f, int32_t jg_begin, int32_t jg_count)
 {
@@ -608,11 +655,11 @@ void tile_kernel(FrameArgs f, int32_t jg_begin, int32_t jg_count)
     if (item >= (int64_t)f.g.nTY * jg_count) return;      // whole wave leaves together
     const int i = (int)(item / jg_count);
     const int jg = jg_begin + (int)(item - (int64_t)i * jg_count);
-    tile_body<BPL, TX, BC, NT, GUARD>(f, i, jg, threadIdx.x % kWave);
+    tile_body<BPL, TX, BC, NT, GUARD, TABLE>(f, i, jg, threadIdx.x % kWave);
 }
 
 // Persistent form: each wave strides over the work items of all jobs.
-template <int BPL, int TX, int BC, bool NT, bool GUARD>
+template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE>
 __global__ __launch_bounds__(kWave * kWavesPerBlock)
 void tile_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs,
                        int32_t njobs, int64_t nitems)
@@ -625,7 +672,7 @@ void tile_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restri
         const int i = (int)(local / jb.jg_count);
         const int jg = jb.jg_begin + (int)(local - (int64_t)i * jb.jg_count);
         const FrameArgs f = cload(frames, jb.frame);
-        tile_body<BPL, TX, BC, NT, GUARD>(f, i, jg, threadIdx.x % kWave);
+        tile_body<BPL, TX, BC, NT, GUARD, TABLE>(f, i, jg, threadIdx.x % kWave);
     }
 }
 
@@ -685,6 +732,16 @@ void query_kernel(const uint32_t* __restrict__ ih_, int32_t H, int32_t W, int32_
     }
 }
 
+// A bin table passed by value as a kernel argument, written to device memory.
+struct LutArg {
+    uint32_t w[64];
+};
+__global__ __launch_bounds__(kWave)
+void lut_store_kernel(LutArg a, uint32_t* dst)
+{
+    dst[threadIdx.x] = a.w[threadIdx.x];
+}
+
 // ---------------------------------------------------------------------------
 // host side: kernel table and launches (geometry and tile choice live in
 // ih_geom.cpp)
@@ -695,11 +752,22 @@ struct TileFns {
     const void* batch;
 };
 
-template <int BPL, int TX, int BC, bool NT, bool GUARD>
+template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE = false>
 static TileFns fns_of()
 {
-    return TileFns{reinterpret_cast<const void*>(&tile_kernel<BPL, TX, BC, NT, GUARD>),
-                   reinterpret_cast<const void*>(&tile_batch_kernel<BPL, TX, BC, NT, GUARD>)};
+    return TileFns{reinterpret_cast<const void*>(&tile_kernel<BPL, TX, BC, NT, GUARD, TABLE>),
+                   reinterpret_cast<const void*>(&tile_batch_kernel<BPL, TX, BC, NT, GUARD, TABLE>)};
+}
+
+// Frames binned by a table: runtime B and regular stores only.
+template <bool GUARD>
+static TileFns pick_table(const TileVariant& v)
+{
+    switch (v.bpl) {
+    case 1: return v.tx == 32 ? fns_of<1, 32, 0, false, GUARD, true>() : fns_of<1, 64, 0, false, GUARD, true>();
+    case 2: return v.tx == 32 ? fns_of<2, 32, 0, false, GUARD, true>() : fns_of<2, 64, 0, false, GUARD, true>();
+    default: return fns_of<4, 32, 0, false, GUARD, true>();
+    }
 }
 
 template <int BPL, int TX, bool NT, bool GUARD>
@@ -733,6 +801,7 @@ static TileFns pick_v(const TileVariant& v)
 
 static TileFns tile_fns(const TileVariant& v)
 {
+    if (v.table) return v.guard ? pick_table<true>(v) : pick_table<false>(v);
     if (v.nt) return v.guard ? pick_v<true, true>(v) : pick_v<true, false>(v);
     return v.guard ? pick_v<false, true>(v) : pick_v<false, false>(v);
 }
@@ -778,7 +847,7 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
             if (count <= 0) continue;
             const int64_t items = (int64_t)g.nTY * count;
             const unsigned blocks = (unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock);
-            const TileFns fn = tile_fns(tile_variant(g, nontemporal, p == 1));
+            const TileFns fn = tile_fns(tile_variant(g, nontemporal, p == 1, f.lut != nullptr));
             FrameArgs fa = f;
             void* args[] = {&fa, &begin, &count};
             hipError_t e = hipLaunchKernel(fn.single, dim3(blocks), dim3(kWave * kWavesPerBlock),
@@ -855,6 +924,14 @@ int32_t tile_resident_blocks(const TileVariant& v)
         per_cu < 1)
         per_cu = 1;
     return cus * per_cu;
+}
+
+hipError_t launch_lut_store(const uint8_t* lut_host, uint32_t* dst, hipStream_t stream)
+{
+    LutArg a;
+    memcpy(a.w, lut_host, sizeof a.w);
+    hipLaunchKernelGGL(lut_store_kernel, dim3(1), dim3(kWave), 0, stream, a, dst);
+    return hipGetLastError();
 }
 
 hipError_t launch_query(const uint32_t* ih, int32_t H, int32_t W, int32_t B,

@@ -121,7 +121,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         const int32_t parts[2][2] = {{0, n_int}, {n_int, g.nJG - n_int}};
         for (int q = 0; q < 2; ++q) {
             if (parts[q][1] <= 0) continue;
-            const TileVariant v = tile_variant(g, nontemporal[k] != 0, q == 1);
+            const TileVariant v = tile_variant(g, nontemporal[k] != 0, q == 1, frames[k].lut != nullptr);
             int64_t& b = items[v];
             byv[v].push_back(Job{b, (int32_t)k, parts[q][0], parts[q][1], 0});
             b += (int64_t)g.nTY * parts[q][1];

@@ -93,3 +93,19 @@ def test_transfer_pipeline_rejects_bad_arguments_before_launch(lib):
     assert f(one, one, 1, 4, 4, 300, 2, None) == 1
     assert f(one, one, 1, 65536, 65536, 8, 2, None) == 2       # H*W = 2^32
     assert f(two, null_entry, 2, 4, 4, 8, 2, None) == 1        # null output pointer
+
+
+def test_compute_lut_rejects_bad_tables_before_launch(lib):
+    f = lib.ih_compute_lut
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    fake = 0x1000  # never dereferenced: validation fails first
+    good = (ctypes.c_uint8 * 256)(*[v * 4 // 256 for v in range(256)])
+    too_big = (ctypes.c_uint8 * 256)(*([0] * 255 + [4]))
+    decreasing = (ctypes.c_uint8 * 256)(*([1] * 128 + [0] * 128))
+    assert f(fake, 4, 4, 4, None, fake, None) == 1
+    assert f(None, 4, 4, 4, good, fake, None) == 1
+    assert f(fake, 4, 4, 4, too_big, fake, None) == 1
+    assert f(fake, 4, 4, 4, decreasing, fake, None) == 1
+    assert f(fake, 0, 4, 4, good, fake, None) == 1
+    assert f(fake, 4, 4, 4, good, fake + 2, None) == 1

@@ -1,0 +1,85 @@
+"""Bins given by a table (ih_compute_lut): the pixel of value v counts in bin
+lut[v], with 256 non-decreasing entries below B -- bins of arbitrary edges,
+some possibly empty.  Bit-exact against the oracle's table recursion
+(tolerance 0) on ragged shapes that span several tiles, and the uniform table
+gives exactly ih_compute's result."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ihb():
+    from paper_1711_01919_amd import binding
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return binding
+
+
+def monotone_lut(rng, B):
+    edges = np.sort(rng.integers(0, 257, size=B - 1))
+    return np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8)
+
+
+SHAPES = [(1, 1), (17, 31), (65, 129), (97, 203), (480, 640)]
+
+
+@pytest.mark.parametrize("B", [1, 3, 16, 32, 64, 100, 128, 256])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_table_bins_equal_oracle(ihb, orc, B, shape):
+    H, W = shape
+    rng = np.random.default_rng(B * 7919 + H * 31 + W)
+    I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    lut = monotone_lut(rng, B)
+    out = ihb.compute_lut(torch.from_numpy(I).cuda(), B, lut)
+    assert np.array_equal(out.cpu().numpy(), orc.integral_histogram_lut(I, B, lut))
+
+
+def test_uniform_table_equals_compute(ihb):
+    rng = np.random.default_rng(50)
+    for (H, W, B) in ((101, 203, 32), (480, 640, 64), (64, 1920, 128)):
+        I = torch.from_numpy(rng.integers(0, 256, size=(H, W), dtype=np.uint8)).cuda()
+        q = ((np.arange(256) * B) >> 8).astype(np.uint8)
+        a = ihb.compute_lut(I, B, q)
+        b = ihb.compute(I, B)
+        torch.cuda.synchronize()
+        assert bool(torch.equal(a.view(torch.int32), b.view(torch.int32)))
+
+
+def test_one_bin_and_empty_bins(ihb, orc):
+    rng = np.random.default_rng(51)
+    I = rng.integers(0, 256, size=(70, 90), dtype=np.uint8)
+    lut = np.zeros(256, np.uint8)
+    lut[250:] = 9                                  # bins 1..8 empty, bin 9 holds 250..255
+    out = ihb.compute_lut(torch.from_numpy(I).cuda(), 10, lut).cpu().numpy()
+    assert np.array_equal(out, orc.integral_histogram_lut(I, 10, lut))
+    assert not out[..., 1:9].any()
+    allzero = np.zeros(256, np.uint8)              # every pixel in bin 0
+    out = ihb.compute_lut(torch.from_numpy(I).cuda(), 4, allzero).cpu().numpy()
+    xy = (np.arange(70)[:, None] + 1) * (np.arange(90)[None, :] + 1)
+    assert np.array_equal(out[..., 0], xy) and not out[..., 1:].any()
+
+
+def test_tables_change_between_calls_on_one_stream(ihb, orc):
+    """Each call stages its table in the stream's scratch after the earlier
+    calls' kernels: back-to-back calls with different tables, no sync."""
+    rng = np.random.default_rng(52)
+    I = rng.integers(0, 256, size=(300, 400), dtype=np.uint8)
+    f = torch.from_numpy(I).cuda()
+    luts = [monotone_lut(rng, 24) for _ in range(5)]
+    outs = [ihb.compute_lut(f, 24, lut) for lut in luts]
+    torch.cuda.synchronize()
+    for lut, o in zip(luts, outs):
+        assert np.array_equal(o.cpu().numpy(), orc.integral_histogram_lut(I, 24, lut))
+
+
+def test_full_hd_table_sampled_rows(ihb, orc):
+    rng = np.random.default_rng(53)
+    I = rng.integers(0, 256, size=(1080, 1920), dtype=np.uint8)
+    lut = monotone_lut(rng, 64)
+    out = ihb.compute_lut(torch.from_numpy(I).cuda(), 64, lut)
+    full = orc.integral_histogram_lut(I, 64, lut)
+    for y in (0, 1, 539, 1078, 1079):
+        assert np.array_equal(out[y].cpu().numpy(), full[y]), y
