@@ -56,6 +56,8 @@ class Oracle:
         lib.ihref_Q.restype = ctypes.c_uint32
         lib.ihref_integral_histogram.argtypes = [_u8p, _i64, _i64, _i64, _u32p]
         lib.ihref_integral_histogram.restype = ctypes.c_int
+        lib.ihref_integral_histogram_binmajor.argtypes = [_u8p, _i64, _i64, _i64, _u32p]
+        lib.ihref_integral_histogram_binmajor.restype = ctypes.c_int
         lib.ihref_integral_histogram_lut.argtypes = [_u8p, _i64, _i64, _i64, _u8p, _u32p]
         lib.ihref_integral_histogram_lut.restype = ctypes.c_int
         lib.ihref_integral_rows.argtypes = [_u8p, _i64, _i64, _i64, _i64, _i64, _u32p, _u32p]
@@ -89,6 +91,16 @@ class Oracle:
         H, W = I.shape
         out = np.empty((H, W, B), dtype=np.uint32)
         rc = self.lib.ihref_integral_histogram(p, H, W, B, out.ctypes.data_as(_u32p))
+        if rc != 0:
+            raise ValueError("bad arguments")
+        return out
+
+    def integral_histogram_binmajor(self, I, B: int) -> np.ndarray:
+        """Algorithm 1 in the paper's order, stored bin-major: shape (B, H, W)."""
+        I, p = self._frame(I)
+        H, W = I.shape
+        out = np.empty((B, H, W), dtype=np.uint32)
+        rc = self.lib.ihref_integral_histogram_binmajor(p, H, W, B, out.ctypes.data_as(_u32p))
         if rc != 0:
             raise ValueError("bad arguments")
         return out

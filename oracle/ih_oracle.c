@@ -16,6 +16,8 @@
  *                             (bins of arbitrary edges: the paper states Q as
  *                             membership of I(r,c) in bin b without fixing
  *                             the bins, Sec. 2.1)
+ *   ihref_integral_histogram_binmajor  Algorithm 1 in the paper's own order:
+ *                             bins outermost, stored b x h x w (Sec. 3.1)
  *   ihref_integral_rows       the same recursion continued over a block of
  *                             rows, for frames whose tensor does not fit RAM
  *   ihref_row_by_definition   one row of Eq. 1, summed directly (columns
@@ -103,6 +105,33 @@ int ihref_integral_histogram(const uint8_t* I, int64_t H, int64_t W, int64_t B, 
                 if (q == (uint32_t)b) h += 1u;
 #endif
                 out[(y * W + x) * B + b] = h;
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * Sec. 2.2, Algorithm 1 with the loops in the listing's order -- bin, then
+ * row, then column -- and the tensor stored bin-major, b x h x w, as the
+ * paper lays it out (Sec. 3.1): entry (x, y, b) at (b*H + y)*W + x.
+ * Returns 0 on success, -1 on bad arguments.
+ */
+int ihref_integral_histogram_binmajor(const uint8_t* I, int64_t H, int64_t W, int64_t B, uint32_t* out)
+{
+    if (!I || !out || H <= 0 || W <= 0 || B < 1 || B > 256) return -1;
+    for (int64_t b = 0; b < B; ++b) {
+        uint32_t* P = out + b * H * W;
+        for (int64_t y = 0; y < H; ++y) {
+            for (int64_t x = 0; x < W; ++x) {
+                const uint32_t left = x > 0 ? P[y * W + x - 1] : 0u;
+                const uint32_t up = y > 0 ? P[(y - 1) * W + x] : 0u;
+#if IHREF_MUTANT == 10
+                const uint32_t corner = (x > 0 && y > 0) ? P[(y - 1) * W + x] : 0u;   /* planted: wrong neighbour */
+#else
+                const uint32_t corner = (x > 0 && y > 0) ? P[(y - 1) * W + x - 1] : 0u;
+#endif
+                P[y * W + x] = left + up - corner + (ihref_Q(I[y * W + x], (uint32_t)B) == (uint32_t)b ? 1u : 0u);
             }
         }
     }

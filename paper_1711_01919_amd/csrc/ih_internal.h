@@ -113,6 +113,10 @@ int32_t tile_resident_blocks(const TileVariant& v);
 int64_t scan_a_blocks(const Geom& g);
 int64_t scan_b_blocks(const Geom& g);
 
+// Tile pass writing the bin-major layout (entry (x, y, b) at (b*H + y)*W + x)
+// from the carries of a frame whose geometry has 64-column tiles.
+hipError_t launch_tile_bm(const FrameArgs& f, hipStream_t stream);
+
 // Copy a host bin table (256 bytes, passed by value as a kernel argument) to
 // device memory dst (64 uint32, 4-byte aligned), in stream order.
 hipError_t launch_lut_store(const uint8_t* lut_host, uint32_t* dst, hipStream_t stream);

@@ -732,6 +732,78 @@ void query_kernel(const uint32_t* __restrict__ ih_, int32_t H, int32_t W, int32_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Phase 3, bin-major layout (the paper's b x h x w, Sec. 3.1 Fig. 2)
+// ---------------------------------------------------------------------------
+// Entry (x, y, b) at (b * H + y) * W + x.  One wave per (tile band, 64-column
+// segment, group of BG <= 16 bins, BG a power of two dividing B); lane l owns column
+// x0 + l.  For a row and a bin the in-row prefix across the segment is a
+// ballot of the lanes whose pixel falls in the bin and a count of the set
+// bits below each lane (mbcnt), plus the left carry of the row; the column
+// accumulators V[t] start from the corner and the lane prefix of the top
+// carries.  Stores are 256 contiguous bytes per bin and row.  The carry
+// phases are the same as for the H x W x B layout with 64-column tiles.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t u = (uint32_t)__builtin_amdgcn_ds_bpermute((lane >= d ? lane - d : lane) * 4, (int)v);
+        v += lane >= d ? u : 0u;
+    }
+    return v;
+}
+
+template <int BG>
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+void tile_bm_kernel(FrameArgs f)
+{
+    const Geom& g = f.g;
+    const int B = g.B, H = g.H, W = g.W;
+    const int n_groups = B / BG;
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int64_t nitems = (int64_t)g.nTY * g.nTX * n_groups;
+    if (item >= nitems) return;                           // whole wave leaves together
+    const int lane = threadIdx.x % kWave;
+    const int grp = (int)(item % n_groups);
+    const int64_t tile = item / n_groups;
+    const int i = (int)(tile / g.nTX), j = (int)(tile % g.nTX);
+    const int x0 = j * kWave, x = x0 + lane;
+    const bool valid = x < W;
+    const int y0 = i * g.TY, y1 = min(H, y0 + g.TY);
+    const int b_lo = grp * BG;
+
+    uint32_t V[BG];
+    {
+        const IH_GLOBAL uint32_t* cp = gmem(f.corner) + ((size_t)i * g.nTX + j) * B + b_lo;
+        const IH_GLOBAL uint32_t* tp = gmem(f.colc) + ((size_t)i * W + x) * B + b_lo;
+        const uint32_t corner = lane < BG ? cp[lane] : 0u;     // lane t: corner of bin b_lo + t
+#pragma unroll
+        for (int t = 0; t < BG; ++t) {
+            const uint32_t c = valid ? tp[t] : 0u;
+            V[t] = (uint32_t)__builtin_amdgcn_readlane((int)corner, t) + wave_inclusive_sum(c, lane);
+        }
+    }
+    const IH_GLOBAL uint8_t* frame = gmem(f.frame);
+    const IH_GLOBAL uint32_t* rowc = gmem(f.rowc) + (size_t)j * H * B + b_lo;
+    IH_GLOBAL uint32_t* out = gmem(f.out);
+    const size_t plane = (size_t)H * W;
+    for (int y = y0; y < y1; ++y) {
+        const uint32_t v = valid ? frame[(size_t)y * W + x] : 0u;
+        const uint32_t q = valid ? (v * (uint32_t)B) >> 8 : 0xFFFFu;
+        const uint32_t carry = lane < BG ? rowc[(size_t)y * B + lane] : 0u;   // lane t: left carry of bin b_lo + t
+        IH_GLOBAL uint32_t* orow = out + (size_t)b_lo * plane + (size_t)y * W + x;
+#pragma unroll
+        for (int t = 0; t < BG; ++t) {
+            const bool hit = q == (uint32_t)(b_lo + t);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            V[t] += (uint32_t)__builtin_amdgcn_readlane((int)carry, t) + below + (hit ? 1u : 0u);
+            if (valid) orow[(size_t)t * plane] = V[t];
+        }
+    }
+}
+
 // A bin table passed by value as a kernel argument, written to device memory.
 struct LutArg {
     uint32_t w[64];
@@ -924,6 +996,33 @@ int32_t tile_resident_blocks(const TileVariant& v)
         per_cu < 1)
         per_cu = 1;
     return cus * per_cu;
+}
+
+// Largest power of two up to 16 that divides B: the bins of one bin-major
+// work item (more bins per item keep more ballot masks and carries live than
+// the scalar registers hold).
+static int bm_group(int B)
+{
+    int bg = 16;
+    while (B % bg != 0) bg >>= 1;
+    return bg;
+}
+
+hipError_t launch_tile_bm(const FrameArgs& f, hipStream_t stream)
+{
+    const Geom& g = f.g;
+    const int bg = bm_group(g.B);
+    const int64_t items = (int64_t)g.nTY * g.nTX * (g.B / bg);
+    const unsigned blocks = (unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock);
+    const dim3 grid(blocks), block(kWave * kWavesPerBlock);
+    switch (bg) {
+    case 16: hipLaunchKernelGGL(tile_bm_kernel<16>, grid, block, 0, stream, f); break;
+    case 8: hipLaunchKernelGGL(tile_bm_kernel<8>, grid, block, 0, stream, f); break;
+    case 4: hipLaunchKernelGGL(tile_bm_kernel<4>, grid, block, 0, stream, f); break;
+    case 2: hipLaunchKernelGGL(tile_bm_kernel<2>, grid, block, 0, stream, f); break;
+    default: hipLaunchKernelGGL(tile_bm_kernel<1>, grid, block, 0, stream, f); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_lut_store(const uint8_t* lut_host, uint32_t* dst, hipStream_t stream)

@@ -11,6 +11,7 @@ fix, none of which re-types the oracle's own recursion.
   - Eq. 2 against direct pixel counting and the area invariant;
   - table binning: brute force with the table's one-hot, the uniform table
     equals Q, empty bins stay zero;
+  - bin-major storage: brute force per bin plane;
   - planted mistakes: every mutant build of the oracle must fail a pin.
 """
 import json
@@ -168,6 +169,12 @@ def pin_failures(orc, quick=False):
         if orc.entry(I, B, x, y, b) != ref[y, x, b]:
             fails.append(f"entry-{x}-{y}-{b}")
 
+    # bin-major storage (the paper's order): brute force per bin plane
+    for (H, W, B) in ((1, 1, 1), (4, 7, 3), (9, 5, 16), (7, 8, 256)):
+        I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+        if not np.array_equal(orc.integral_histogram_binmajor(I, B), np.moveaxis(brute_eq1(I, B), 2, 0)):
+            fails.append(f"binmajor-brute-{H}x{W}-B{B}")
+
     # table binning (bins with arbitrary edges, and arbitrary tables): brute
     # force with the table's one-hot, the uniform table equals Q, invariants
     for (H, W, B) in ((1, 1, 1), (3, 7, 3), (9, 4, 16), (6, 6, 7), (5, 9, 256)):
@@ -253,7 +260,7 @@ def test_rejects_bad_arguments(orc):
             orc.region_histogram(IH, np.array([r]))
 
 
-@pytest.mark.parametrize("mutant", range(1, 10))
+@pytest.mark.parametrize("mutant", range(1, 11))
 def test_planted_mistakes_are_caught(tmp_path, mutant):
     """Each planted mistake in the oracle (a rounding binning, a dropped or
     sign-flipped corner term, a lost pixel, an off-by-one corner in Eq. 2, a
