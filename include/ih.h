@@ -82,6 +82,16 @@ ih_status ih_compute(const uint8_t* frame, int32_t H, int32_t W, int32_t B,
                      uint32_t* out, ih_stream_t stream);
 
 /*
+ * ih_compute_binmajor -- as ih_compute, with the result in the paper's
+ * bin-major layout b x h x w (Sec. 3.1, Fig. 2): entry (x, y, b) at
+ * out[(b*H + y)*W + x], so every bin is one contiguous H x W plane.  Same
+ * arguments, errors and scratch as ih_compute; ih_query expects the
+ * H x W x B layout and does not read this one.
+ */
+ih_status ih_compute_binmajor(const uint8_t* frame, int32_t H, int32_t W, int32_t B, uint32_t* out,
+                              ih_stream_t stream);
+
+/*
  * ih_compute_lut -- as ih_compute, with the bins given by a table: the pixel
  * of value v counts in bin lut_host[v].  The paper states the binning only as
  * membership of a pixel value in a bin (Sec. 2.1, the Q of Eq. 1); a table

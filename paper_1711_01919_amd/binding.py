@@ -87,6 +87,8 @@ def _load() -> ctypes.CDLL:
     lib = ctypes.CDLL(str(LIB_PATH))
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     lib.ih_compute.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.ih_compute_binmajor.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.ih_compute_binmajor.restype = ctypes.c_int
     lib.ih_compute_lut.argtypes = [vp, i32, i32, i32, vp, vp, vp]
     lib.ih_compute_lut.restype = ctypes.c_int
     lib.ih_query.argtypes = [ctypes.POINTER(View), vp, sz, vp]
@@ -158,6 +160,21 @@ def compute(frame: torch.Tensor, B: int, out: torch.Tensor | None = None, stream
     elif out.dtype != torch.uint32 or not out.is_contiguous() or out.numel() < H * W * B:
         raise ValueError("out must be a contiguous uint32 tensor with H*W*B elements")
     _check(lib.ih_compute(_ptr(frame), H, W, B, _ptr(out), _stream_handle(stream)), "ih_compute")
+    return out
+
+
+def compute_binmajor(frame: torch.Tensor, B: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """ih_compute_binmajor: the integral histogram in the bin-major layout,
+    a (B, H, W) uint32 tensor."""
+    if frame.dtype != torch.uint8 or frame.dim() != 2 or not frame.is_cuda or not frame.is_contiguous():
+        raise ValueError("frame must be a contiguous 2-D uint8 CUDA tensor")
+    H, W = frame.shape
+    if out is None:
+        out = torch.empty((B, H, W), dtype=torch.uint32, device=frame.device)
+    elif out.dtype != torch.uint32 or not out.is_cuda or not out.is_contiguous() or out.numel() < H * W * B:
+        raise ValueError("out must be a contiguous uint32 CUDA tensor with B*H*W elements")
+    _check(lib.ih_compute_binmajor(_ptr(frame), H, W, int(B), _ptr(out), _stream_handle(stream)),
+           "ih_compute_binmajor")
     return out
 
 

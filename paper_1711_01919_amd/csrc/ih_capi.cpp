@@ -121,6 +121,29 @@ ih_status ih_compute(const uint8_t* frame, int32_t H, int32_t W, int32_t B,
     return enqueue_frame(frame, out, static_cast<uint32_t*>(scratch), g, t.nontemporal, s);
 }
 
+ih_status ih_compute_binmajor(const uint8_t* frame, int32_t H, int32_t W, int32_t B, uint32_t* out,
+                              ih_stream_t stream)
+{
+    if (!frame || !out) return fail(IH_ERR_INVALID_ARG, "frame and out must be non-null");
+    if (ih_status st = ih::check_shape(H, W, B)) return st;
+    if (reinterpret_cast<uintptr_t>(out) & 3u) return fail(IH_ERR_INVALID_ARG, "out must be 4-byte aligned");
+    const ih::Geom g = ih::make_geom(H, W, B, ih::binmajor_tile(H, W, B));
+    void* scratch = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ih_status st = get_scratch(s, ih::scratch_layout(g).words * sizeof(uint32_t), &scratch)) return st;
+    const ih::FrameArgs fa = ih::frame_args(frame, out, static_cast<uint32_t*>(scratch), g);
+    ih::PhaseTimer timer;
+    for (int ph = 0; ph < ih::kNumPhases; ++ph) {
+        if (ih_status st = timer.begin(ph, s)) return st;
+        hipError_t e = ph == static_cast<int>(ih::Phase::kTile) ? ih::launch_tile_bm(fa, s)
+                                                                : ih::launch_phase(static_cast<ih::Phase>(ph), fa, false, s);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        if (ih_status st = timer.end(s)) return st;
+    }
+    if (ih::profiling_on()) ih::profiling_add_frames(1);
+    return IH_OK;
+}
+
 ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, const uint8_t* lut_host,
                          uint32_t* out, ih_stream_t stream)
 {

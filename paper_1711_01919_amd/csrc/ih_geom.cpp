@@ -78,6 +78,16 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B)
     return t;
 }
 
+TileChoice binmajor_tile(int32_t H, int32_t W, int32_t B)
+{
+    int bg = 16;
+    while (B % bg != 0) bg >>= 1;
+    const int64_t cols = (W + 63) / 64, groups = B / bg;
+    int TY = 512;
+    while (TY > 8 && (int64_t)((H + TY - 1) / TY) * cols * groups < 960) TY /= 2;
+    return TileChoice{64, even_band_height(H, TY), false};
+}
+
 int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out)
 {
     const bool aligned = ((reinterpret_cast<uintptr_t>(frame) & 15) == 0) && (g.W % 16 == 0) &&
