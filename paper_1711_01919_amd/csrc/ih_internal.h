@@ -68,7 +68,7 @@ int bins_per_lane(int B);
 Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t);
 TileChoice default_tile(int32_t H, int32_t W, int32_t B);
 // Tile of the bin-major tile pass: 64 columns (one per lane), bands for about
-// 1000 work items of up to 16 bins.
+// 4000 work items of up to 16 bins.
 TileChoice binmajor_tile(int32_t H, int32_t W, int32_t B);
 // The same number of bands as TY gives, made equally tall (the last band is
 // no shorter than the others by more than one row): a short last band makes

@@ -787,19 +787,45 @@ void tile_bm_kernel(FrameArgs f)
     const IH_GLOBAL uint32_t* rowc = gmem(f.rowc) + (size_t)j * H * B + b_lo;
     IH_GLOBAL uint32_t* out = gmem(f.out);
     const size_t plane = (size_t)H * W;
-    for (int y = y0; y < y1; ++y) {
-        const uint32_t v = valid ? frame[(size_t)y * W + x] : 0u;
-        const uint32_t q = valid ? (v * (uint32_t)B) >> 8 : 0xFFFFu;
-        const uint32_t carry = lane < BG ? rowc[(size_t)y * B + lane] : 0u;   // lane t: left carry of bin b_lo + t
-        IH_GLOBAL uint32_t* orow = out + (size_t)b_lo * plane + (size_t)y * W + x;
+    // Pixels (binned) and left carries come 8 rows at a time, a chunk ahead:
+    // lane t holds the carry of bin b_lo + t; rows past the band are clamped.
+    constexpr int CH = 8;
+    uint32_t cq[CH], cc[CH], nq[CH], nc[CH];
+    auto load_chunk = [&](int yc, uint32_t (&q)[CH], uint32_t (&c)[CH]) {
 #pragma unroll
-        for (int t = 0; t < BG; ++t) {
-            const bool hit = q == (uint32_t)(b_lo + t);
-            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            V[t] += (uint32_t)__builtin_amdgcn_readlane((int)carry, t) + below + (hit ? 1u : 0u);
-            if (valid) orow[(size_t)t * plane] = V[t];
+        for (int r = 0; r < CH; ++r) {
+            const int row = min(yc + r, y1 - 1);
+            const uint32_t v = valid ? frame[(size_t)row * W + x] : 0u;
+            q[r] = valid ? (v * (uint32_t)B) >> 8 : 0xFFFFu;
+            c[r] = lane < BG ? rowc[(size_t)row * B + lane] : 0u;
+        }
+    };
+    load_chunk(y0, cq, cc);
+    for (int yc = y0; yc < y1; yc += CH) {
+        const bool more = yc + CH < y1;
+        if (more) load_chunk(yc + CH, nq, nc);
+#pragma unroll
+        for (int r = 0; r < CH; ++r) {
+            const int y = yc + r;
+            if (y < y1) {
+                IH_GLOBAL uint32_t* orow = out + (size_t)b_lo * plane + (size_t)y * W + x;
+#pragma unroll
+                for (int t = 0; t < BG; ++t) {
+                    const bool hit = cq[r] == (uint32_t)(b_lo + t);
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    V[t] += (uint32_t)__builtin_amdgcn_readlane((int)cc[r], t) + below + (hit ? 1u : 0u);
+                    if (valid) orow[(size_t)t * plane] = V[t];
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int r = 0; r < CH; ++r) {
+                cq[r] = nq[r];
+                cc[r] = nc[r];
+            }
         }
     }
 }
