@@ -40,9 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # reads on the same counters).  Valid only for the kernel source and tile they
 # were taken with; any other combination reports null.
 TRAFFIC_RECORD = {
-    "kernel_src_sha256": "786d007de250cfb1fac580ed8cb9b58e7d88a5b7896643d24c27c3e8cc7164c3",
+    "kernel_src_sha256": "af6e8cfbcaf773008859c44e22b619198fae96445fc7e72680bf62fb286646b6",
     "workload": "disc_sequence_64x1080x1920_B64", "tile": [128, 216], "nontemporal": False,
-    "fetch_bytes": 336934.8 * 2.0 * 1024, "write_bytes": 33177600.0 * 1.0 * 1024,
+    "fetch_bytes": 336930.1 * 2.0 * 1024, "write_bytes": 33177600.0 * 1.0 * 1024,
 }
 
 
@@ -192,6 +192,24 @@ def plain_and_query_legs(torch, ihb, synth, stream) -> dict:
                                       "hbm_frac": (H * W + 4 * H * W * B) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                                       "calls": reps, "rotating_outputs": 8, "query_1000_rects_ms": qms}
     del f, ihs, rd, hs
+    # the other single-frame forms on one 1920x1080 disc frame, B=64: the
+    # bin-major layout and bins from a table (random edges, seed 4)
+    frames1, B1 = synth.disc_sequence(n_frames=1)
+    f1 = torch.from_numpy(frames1[0]).cuda()
+    H1, W1 = frames1.shape[1:]
+    o1 = torch.empty((H1, W1, B1), dtype=torch.uint32, device="cuda")
+    edges = np.sort(np.random.default_rng(4).integers(0, 257, size=B1 - 1))
+    lut = np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8)
+    by1 = H1 * W1 + 4 * H1 * W1 * B1
+    forms = {}
+    for name, fn in (("hwb", lambda: ihb.compute(f1, B1, out=o1, stream=stream)),
+                     ("binmajor", lambda: ihb.compute_binmajor(f1, B1, out=o1, stream=stream)),
+                     ("table_bins", lambda: ihb.compute_lut(f1, B1, lut, out=o1, stream=stream))):
+        fn()
+        ms1 = timed(torch, stream, fn, 50) / 50
+        forms[name] = {"ms_per_frame": ms1, "hbm_frac": by1 / (ms1 / 1e3) / 1e9 / HBM_PEAK_GBS}
+    out["single_frame_1920x1080_B64_forms"] = forms
+    del f1, o1
     I, B, rects = synth.mixture_frame()
     H, W = I.shape
     f = torch.from_numpy(I).cuda()
