@@ -16,8 +16,10 @@ Prints ONE JSON line: throughput (entries/s) of the batched step; the same
 frames through 64 plain per-frame ih_compute calls for comparison; the
 roofline of the dominant kernel (the tile pass, HBM-bound); the 640x480
 B=32 frame and the 8192x8192 B=128 frame through ih_compute with their
-region queries; the host-transfer pipeline (frames/s with the whole integral
-histogram copied back over PCIe, as the paper measures); the serving loop's
+region queries; one 1920x1080 B=64 frame in the H x W x B layout, the
+bin-major layout and with bins from a table; the host-transfer pipeline
+(frames/s with the whole integral histogram copied back over PCIe, as the
+paper measures); a device write reference (torch fill); the serving loop's
 p50/p99 latency and
 throughput on a replayed 16-stream trace next to the plain per-frame path;
 and the single-threaded CPU oracle timed on a bounded sample of the batched

@@ -143,6 +143,11 @@ typedef struct {
     const uint8_t* frame;       /* device, H*W uint8, row-major              */
     uint32_t* out;              /* device, H*W*B uint32 (layout above)        */
     int32_t H, W, B;
+    const uint8_t* lut;         /* host, NULL for the uniform bins, else a bin
+                                   table as for ih_compute_lut (256 entries,
+                                   non-decreasing, each < B), copied when the
+                                   plan is created; such frames take tiles at
+                                   most 64 wide and are not autotuned         */
 } ih_frame_desc;
 
 typedef struct {

@@ -40,6 +40,9 @@ struct ih_batch_plan {
     std::vector<ih::TileChoice> tiles;
     void* d_scratch = nullptr;
     void* d_image = nullptr;
+    std::vector<uint8_t> luts;            // copies of the frames' bin tables, 256 bytes each
+    std::vector<int32_t> lut_index;       // per frame: index into luts, or -1 (uniform bins)
+    void* d_luts = nullptr;
     ih::BatchImage image;                 // one group: every frame
     std::vector<PlanGroup> groups;        // two or more: the pipelined form
     int64_t group_bytes = 0;              // requested (options), resolved at build
@@ -102,6 +105,7 @@ void free_plan(ih_batch_plan* p)
     if (p->ev_start) (void)hipEventDestroy(p->ev_start);
     if (p->side) (void)hipStreamDestroy(p->side);
     if (p->d_image) (void)hipFree(p->d_image);
+    if (p->d_luts) (void)hipFree(p->d_luts);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     delete p;
 }
@@ -134,12 +138,23 @@ ih_status build_plan(ih_batch_plan* p)
         (void)hipGetLastError();
         return fail(IH_ERR_OOM, "batch scratch of %zu bytes: %s", words * 4, hipGetErrorString(e));
     }
+    if (!p->luts.empty()) {
+        e = hipMalloc(&p->d_luts, p->luts.size());
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(IH_ERR_OOM, "bin tables: %s", hipGetErrorString(e));
+        }
+        e = hipMemcpy(p->d_luts, p->luts.data(), p->luts.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload bin tables");
+    }
     std::vector<ih::FrameArgs> frames(n);
     std::vector<char> nt(n);
     int64_t total_out = 0;
     for (size_t k = 0; k < n; ++k) {
+        const int32_t li = p->lut_index.empty() ? -1 : p->lut_index[k];
+        const uint8_t* dl = li < 0 ? nullptr : static_cast<const uint8_t*>(p->d_luts) + (size_t)li * 256;
         frames[k] = ih::frame_args(p->descs[k].frame, p->descs[k].out,
-                                   static_cast<uint32_t*>(p->d_scratch) + off[k], geoms[k]);
+                                   static_cast<uint32_t*>(p->d_scratch) + off[k], geoms[k], dl);
         nt[k] = p->tiles[k].nontemporal ? 1 : 0;
         total_out += (int64_t)p->descs[k].H * p->descs[k].W * p->descs[k].B * 4;
     }
@@ -363,7 +378,8 @@ ih_status autotune(ih_batch_plan* p, hipStream_t s)
 {
     std::map<TuneKey, std::vector<size_t>> classes;
     for (size_t k = 0; k < p->descs.size(); ++k)
-        classes[TuneKey{p->descs[k].H, p->descs[k].W, p->descs[k].B, 0}].push_back(k);
+        if (p->descs[k].lut == nullptr)                       // frames with bin tables keep their heuristic tile
+            classes[TuneKey{p->descs[k].H, p->descs[k].W, p->descs[k].B, 0}].push_back(k);
     TuneCache& c = tune_cache();
     std::lock_guard<std::mutex> lock(c.mu);
     load_cache(c);
@@ -414,10 +430,27 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
         if (reinterpret_cast<uintptr_t>(d.out) & 3u) return fail(IH_ERR_INVALID_ARG, "frame %zu: out misaligned", k);
         if (forced && !ih::tile_supported(d.B, ih::TileChoice{o.tile_x, o.tile_y, false}))
             return fail(IH_ERR_INVALID_ARG, "tile %dx%d not supported for B=%d", o.tile_x, o.tile_y, d.B);
+        if (d.lut) {
+            if (forced && o.tile_x > 64)
+                return fail(IH_ERR_INVALID_ARG, "frame %zu: bin tables take tiles at most 64 wide", k);
+            for (int v = 0; v < 256; ++v) {
+                if ((int32_t)d.lut[v] >= d.B)
+                    return fail(IH_ERR_INVALID_ARG, "frame %zu: lut[%d]=%d is not a bin below B=%d", k, v, d.lut[v], d.B);
+                if (v > 0 && d.lut[v] < d.lut[v - 1])
+                    return fail(IH_ERR_INVALID_ARG, "frame %zu: lut decreases at %d", k, v);
+            }
+        }
     }
     ih_batch_plan* p = new ih_batch_plan;
     (void)hipGetDevice(&p->device);
     p->descs.assign(frames, frames + n);
+    for (size_t k = 0; k < n; ++k) {
+        if (frames[k].lut) {
+            if (p->lut_index.empty()) p->lut_index.assign(n, -1);
+            p->lut_index[k] = (int32_t)(p->luts.size() / 256);
+            p->luts.insert(p->luts.end(), frames[k].lut, frames[k].lut + 256);
+        }
+    }
     p->use_graph = o.use_graph != 0;
     p->group_bytes = o.group_bytes;
     p->tiles.resize(n);
@@ -428,9 +461,9 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     ih_status st = IH_OK;
     if (forced) {
         for (size_t k = 0; k < n; ++k) p->tiles[k] = ih::TileChoice{o.tile_x, o.tile_y, false};
-    } else if (o.autotune) {
-        st = autotune(p, s);
     } else {
+        // the heuristic for every frame; the autotuner then replaces the
+        // tiles of the frames it times (those with uniform bins)
         std::map<int32_t, std::vector<ih_frame_desc>> by_b;
         for (size_t k = 0; k < n; ++k) by_b[frames[k].B].push_back(frames[k]);
         std::map<int32_t, ih::TileChoice> choice;
@@ -444,9 +477,18 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
             choice[kv.first].nontemporal = ng > 1;
         }
         for (size_t k = 0; k < n; ++k) p->tiles[k] = choice[frames[k].B];
+        if (o.autotune) st = autotune(p, s);
     }
     if (st == IH_OK && o.nontemporal >= 0)
         for (auto& t : p->tiles) t.nontemporal = o.nontemporal != 0;
+    // Frames with bin tables: the table kernels exist for tiles up to 64 wide
+    // (regular stores); the caller's table pointers are not kept.
+    for (size_t k = 0; st == IH_OK && k < n; ++k) {
+        if (!p->descs[k].lut) continue;
+        if (p->tiles[k].TX > 64) p->tiles[k].TX = 64;
+        p->tiles[k].nontemporal = false;
+        p->descs[k].lut = nullptr;
+    }
     if (st == IH_OK) st = build_plan(p);
     if (st == IH_OK && p->use_graph) {
         st = capture(p, -1, &p->exec_all);

@@ -109,3 +109,20 @@ def test_compute_lut_rejects_bad_tables_before_launch(lib):
     assert f(fake, 4, 4, 4, decreasing, fake, None) == 1
     assert f(fake, 0, 4, 4, good, fake, None) == 1
     assert f(fake, 4, 4, 4, good, fake + 2, None) == 1
+
+
+def test_batch_plan_rejects_bad_tables_before_launch(lib):
+    class FrameDesc(ctypes.Structure):
+        _fields_ = [("frame", ctypes.c_void_p), ("out", ctypes.c_void_p), ("H", ctypes.c_int32),
+                    ("W", ctypes.c_int32), ("B", ctypes.c_int32), ("lut", ctypes.c_void_p)]
+    f = lib.ih_batch_plan_create
+    f.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_void_p)]
+    fake = 0x1000  # never dereferenced: validation fails first
+    decreasing = (ctypes.c_uint8 * 256)(*([2] * 100 + [1] * 156))
+    too_big = (ctypes.c_uint8 * 256)(*([0] * 255 + [8]))
+    plan = ctypes.c_void_p()
+    for table in (decreasing, too_big):
+        d = (FrameDesc * 1)(FrameDesc(fake, fake, 4, 4, 8, ctypes.cast(table, ctypes.c_void_p)))
+        assert f(d, 1, None, None, ctypes.byref(plan)) == 1
+        assert not plan.value

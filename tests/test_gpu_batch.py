@@ -219,3 +219,41 @@ def test_bad_descriptors_rejected(ihb):
     o32 = torch.zeros((8, 8, 32), dtype=torch.uint32, device="cuda")
     with pytest.raises(ihb.IHError):
         ihb.BatchPlan([f], [o32], [32], tile=(128, 16))
+
+
+@pytest.mark.parametrize("group_bytes,use_graph,autotune", [(0, True, False), (40 << 20, True, False), (0, False, True)])
+def test_plan_with_bin_tables(ihb, orc, group_bytes, use_graph, autotune):
+    """Frames with bin tables next to frames with uniform bins in one plan
+    (graphed, pipelined, autotuned): each equals the oracle's result for its
+    binning; the tables are copied at creation (the caller's are overwritten
+    right after)."""
+    rng = np.random.default_rng(26)
+    shapes = [(240, 320, 64), (97, 203, 32), (360, 640, 16), (61, 64, 128), (240, 320, 64), (130, 257, 7),
+              (480, 640, 64)]
+    frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _ in shapes]
+    bins = [b for _, _, b in shapes]
+    luts = []
+    for k, b in enumerate(bins):
+        if k % 2 == 0:
+            edges = np.sort(rng.integers(0, 257, size=b - 1))
+            luts.append(np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8))
+        else:
+            luts.append(None)
+    refs = [orc.integral_histogram(f, b) if t is None else orc.integral_histogram_lut(f, b, t)
+            for f, b, t in zip(frames, bins, luts)]
+    fr, outs = to_dev(frames, bins)
+    plan = ihb.BatchPlan(fr, outs, bins, use_graph=use_graph, group_bytes=group_bytes, autotune=autotune,
+                         luts=[None if t is None else t.copy() for t in luts])
+    for k, t in enumerate(luts):
+        if t is not None:
+            tx, _, nt = plan.frame_tile(k)
+            assert tx <= 64 and not nt
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for k in range(len(frames)):
+            assert np.array_equal(outs[k].cpu().numpy(), refs[k]), (rep, k)
+    plan.close()
