@@ -26,6 +26,7 @@
 // sorted job table and run the same body.
 #include "ih_internal.h"
 
+#include <algorithm>
 #include <cstring>
 
 namespace ih {
@@ -91,7 +92,7 @@ __device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs,
 // counters: a segment holds at most TX <= 128 pixels), then each lane walks
 // the segments for its bins and stores the exclusive running count: rowc[j][y][b]
 // = pixels of row y left of segment j in bin b.
-constexpr int kSegChunk = 64;
+constexpr int kSegChunk = 32;
 constexpr int kRowThreads = kWave;     // one row per workgroup
 
 __device__ __forceinline__ void lds_inc8(uint32_t* h, uint32_t e)
@@ -127,11 +128,22 @@ __device__ __forceinline__ uint32_t lut_count_below(const IH_GLOBAL uint8_t* lut
     return pos;
 }
 
+// The row-carry work is one wave's own: its LDS region is private and it
+// synchronizes within the wave only (all memory counters drained), so a
+// workgroup may hold several row waves, or row waves beside other work.
+__device__ __forceinline__ void wave_sync()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uint32_t* lds)
 {
     const Geom& g = f.g;
     const int B = g.B, TX = g.TX, bpl = g.BPL;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
     uint32_t run[4] = {0u, 0u, 0u, 0u};
     const IH_GLOBAL uint8_t* prow = gmem(f.frame) + y * g.W;
     // rowc is segment-major, [j][y][b]: a tile wave's rows are contiguous
@@ -145,7 +157,7 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
     for (int j0 = 0; j0 < g.nTX; j0 += kSegChunk) {
         const int ns = min(kSegChunk, g.nTX - j0);
         for (int w = lane; w < (ns * B + 3) / 4; w += kRowThreads) lds[w] = 0u;
-        __syncthreads();
+        wave_sync();
         const int x0 = j0 * TX;
         const int npx = min(ns * TX, g.W - x0);
         const int nchunks = (npx + 15) / 16;
@@ -181,7 +193,7 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         for (int s = 0; s < ns; ++s) {
             IH_GLOBAL uint32_t* o = out + (size_t)(j0 + s) * seg_stride;
             for (int t = 0; t < bpl; ++t) {
@@ -192,7 +204,7 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -303,6 +315,32 @@ void agg_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restric
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
     agg_body<TX>(f, (int64_t)blockIdx.x - jb.begin, colh, lutw);
+}
+
+// Phase 1 of a single frame in one launch: blocks [0, row_blocks) hold four
+// row-carry waves each (rows 4 b .. 4 b + 3), the other blocks one tile of
+// column counts each; both kinds run side by side and use the dynamic LDS
+// buffer by role.
+constexpr int kRowsPerCountBlock = kAggThreads / kWave;
+
+__host__ __device__ inline size_t agg_lds_bytes(int TX, int B)
+{
+    return ((size_t)TX * B + 1) / 2 * 4 + 256;
+}
+
+template <int TX>
+__global__ __launch_bounds__(kAggThreads)
+void count_kernel(FrameArgs f, int32_t row_blocks)
+{
+    extern __shared__ uint32_t lds[];
+    if ((int32_t)blockIdx.x < row_blocks) {
+        const int w = wave_in_block();
+        const int64_t y = (int64_t)blockIdx.x * kRowsPerCountBlock + w;
+        if (y < f.g.H) rowcarry_body(f, y, lds + (size_t)w * (rowcarry_lds_bytes(f.g) / 4));
+        return;
+    }
+    uint32_t* colh = lds;
+    agg_body<TX>(f, (int64_t)blockIdx.x - row_blocks, colh, colh + ((size_t)TX * f.g.B + 1) / 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -922,15 +960,15 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
     const Geom& g = f.g;
     switch (ph) {
     case Phase::kAgg: {
-        hipLaunchKernelGGL(rowcarry_kernel, dim3((unsigned)g.H), dim3(kRowThreads),
-                           (unsigned)rowcarry_lds_bytes(g), stream, f);
-        const unsigned ntiles = (unsigned)g.nTX * (unsigned)g.nTY;
+        const int32_t row_blocks = (g.H + kRowsPerCountBlock - 1) / kRowsPerCountBlock;
+        const unsigned blocks = (unsigned)row_blocks + (unsigned)g.nTX * (unsigned)g.nTY;
+        const size_t lds = std::max(kRowsPerCountBlock * rowcarry_lds_bytes(g), agg_lds_bytes(g.TX, g.B));
         if (g.TX == 32)
-            hipLaunchKernelGGL(agg_kernel<32>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
+            hipLaunchKernelGGL(count_kernel<32>, dim3(blocks), dim3(kAggThreads), (unsigned)lds, stream, f, row_blocks);
         else if (g.TX == 128)
-            hipLaunchKernelGGL(agg_kernel<128>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
+            hipLaunchKernelGGL(count_kernel<128>, dim3(blocks), dim3(kAggThreads), (unsigned)lds, stream, f, row_blocks);
         else
-            hipLaunchKernelGGL(agg_kernel<64>, dim3(ntiles), dim3(kAggThreads), 0, stream, f);
+            hipLaunchKernelGGL(count_kernel<64>, dim3(blocks), dim3(kAggThreads), (unsigned)lds, stream, f, row_blocks);
         break;
     }
     case Phase::kScan:
