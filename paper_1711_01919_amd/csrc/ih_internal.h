@@ -53,7 +53,7 @@ FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, con
 struct Job {
     int64_t begin;
     int32_t frame;       // index into the FrameArgs table
-    int32_t jg_begin;    // tile pass: first column group of the job
+    int32_t jg_begin;    // tile pass: first column group of the job; count phase: row-carry blocks
     int32_t jg_count;    // tile pass: column groups per tile band
     int32_t pad;
 };
@@ -96,12 +96,13 @@ constexpr int kNumPhases = 3;
 hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStream_t stream);
 
 // ---- batched launches over a device FrameArgs table ----------------------
-hipError_t launch_agg_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
-                            int64_t nblocks, hipStream_t stream);
-hipError_t launch_rowcarry_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
-                                 int64_t nblocks, size_t lds_bytes, hipStream_t stream);
-// LDS bytes the row-carry kernel needs for a frame.
-size_t rowcarry_lds(const Geom& g);
+// Count phase (row carries + tile column counts) of many frames of tile width
+// TX in one launch; a job's jg_begin holds its frame's row-carry block count.
+hipError_t launch_count_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                              int64_t nblocks, size_t lds_bytes, hipStream_t stream);
+// Row-carry blocks (four rows each) and dynamic LDS bytes of a frame's count phase.
+int32_t count_row_blocks(const Geom& g);
+size_t count_lds(const Geom& g);
 hipError_t launch_scan_a_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
                                int64_t nblocks, hipStream_t stream);
 hipError_t launch_scan_b_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,

@@ -93,7 +93,7 @@ __device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs,
 // the segments for its bins and stores the exclusive running count: rowc[j][y][b]
 // = pixels of row y left of segment j in bin b.
 constexpr int kSegChunk = 32;
-constexpr int kRowThreads = kWave;     // one row per workgroup
+constexpr int kRowThreads = kWave;     // one row per wave
 
 __device__ __forceinline__ void lds_inc8(uint32_t* h, uint32_t e)
 {
@@ -216,22 +216,6 @@ __host__ __device__ inline size_t rowcarry_lds_bytes(const Geom& g)
     return ((size_t)ns * g.B + 3) / 4 * 4 + 256;
 }
 
-__global__ __launch_bounds__(kRowThreads)
-void rowcarry_kernel(FrameArgs f)
-{
-    extern __shared__ uint32_t lds[];
-    rowcarry_body(f, blockIdx.x, lds);
-}
-
-__global__ __launch_bounds__(kRowThreads)
-void rowcarry_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
-{
-    extern __shared__ uint32_t lds[];
-    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
-    const FrameArgs f = cload(frames, jb.frame);
-    rowcarry_body(f, (int64_t)blockIdx.x - jb.begin, lds);
-}
-
 // ---------------------------------------------------------------------------
 // Phase 1b: per-tile column counts (agg)
 // ---------------------------------------------------------------------------
@@ -293,34 +277,11 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     }
 }
 
-// Largest B that a TX-wide tile supports (128-wide tiles are for B = 64).
-template <int TX>
-constexpr int agg_max_bins() { return TX == 128 ? 64 : 256; }
-
-template <int TX>
-__global__ __launch_bounds__(kAggThreads)
-void agg_kernel(FrameArgs f)
-{
-    __shared__ uint32_t colh[TX * agg_max_bins<TX>() / 2];
-    __shared__ uint32_t lutw[64];
-    agg_body<TX>(f, blockIdx.x, colh, lutw);
-}
-
-template <int TX>
-__global__ __launch_bounds__(kAggThreads)
-void agg_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
-{
-    __shared__ uint32_t colh[TX * agg_max_bins<TX>() / 2];
-    __shared__ uint32_t lutw[64];
-    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
-    const FrameArgs f = cload(frames, jb.frame);
-    agg_body<TX>(f, (int64_t)blockIdx.x - jb.begin, colh, lutw);
-}
-
 // Phase 1 of a single frame in one launch: blocks [0, row_blocks) hold four
 // row-carry waves each (rows 4 b .. 4 b + 3), the other blocks one tile of
 // column counts each; both kinds run side by side and use the dynamic LDS
-// buffer by role.
+// buffer by role.  The batched form does the same per frame: a job's jg_begin
+// holds its frame's row-block count, followed by the frame's tile blocks.
 constexpr int kRowsPerCountBlock = kAggThreads / kWave;
 
 __host__ __device__ inline size_t agg_lds_bytes(int TX, int B)
@@ -341,6 +302,24 @@ void count_kernel(FrameArgs f, int32_t row_blocks)
     }
     uint32_t* colh = lds;
     agg_body<TX>(f, (int64_t)blockIdx.x - row_blocks, colh, colh + ((size_t)TX * f.g.B + 1) / 2);
+}
+
+template <int TX>
+__global__ __launch_bounds__(kAggThreads)
+void count_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
+{
+    extern __shared__ uint32_t lds[];
+    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
+    const FrameArgs f = cload(frames, jb.frame);
+    const int64_t local = (int64_t)blockIdx.x - jb.begin;
+    if (local < jb.jg_begin) {
+        const int w = wave_in_block();
+        const int64_t y = local * kRowsPerCountBlock + w;
+        if (y < f.g.H) rowcarry_body(f, y, lds + (size_t)w * (rowcarry_lds_bytes(f.g) / 4));
+        return;
+    }
+    uint32_t* colh = lds;
+    agg_body<TX>(f, local - jb.jg_begin, colh, colh + ((size_t)TX * f.g.B + 1) / 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -942,7 +921,6 @@ static TileFns tile_fns(const TileVariant& v)
     return v.guard ? pick_v<false, true>(v) : pick_v<false, false>(v);
 }
 
-size_t rowcarry_lds(const Geom& g) { return rowcarry_lds_bytes(g); }
 
 int64_t scan_a_blocks(const Geom& g)
 {
@@ -960,9 +938,9 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
     const Geom& g = f.g;
     switch (ph) {
     case Phase::kAgg: {
-        const int32_t row_blocks = (g.H + kRowsPerCountBlock - 1) / kRowsPerCountBlock;
+        const int32_t row_blocks = count_row_blocks(g);
         const unsigned blocks = (unsigned)row_blocks + (unsigned)g.nTX * (unsigned)g.nTY;
-        const size_t lds = std::max(kRowsPerCountBlock * rowcarry_lds_bytes(g), agg_lds_bytes(g.TX, g.B));
+        const size_t lds = count_lds(g);
         if (g.TX == 32)
             hipLaunchKernelGGL(count_kernel<32>, dim3(blocks), dim3(kAggThreads), (unsigned)lds, stream, f, row_blocks);
         else if (g.TX == 128)
@@ -996,28 +974,24 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_agg_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
-                            int64_t nblocks, hipStream_t stream)
+int32_t count_row_blocks(const Geom& g) { return (g.H + kRowsPerCountBlock - 1) / kRowsPerCountBlock; }
+
+size_t count_lds(const Geom& g)
 {
-    if (nblocks <= 0) return hipSuccess;
-    if (TX == 32)
-        hipLaunchKernelGGL(agg_batch_kernel<32>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,
-                           frames, jobs, njobs);
-    else if (TX == 128)
-        hipLaunchKernelGGL(agg_batch_kernel<128>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,
-                           frames, jobs, njobs);
-    else
-        hipLaunchKernelGGL(agg_batch_kernel<64>, dim3((unsigned)nblocks), dim3(kAggThreads), 0, stream,
-                           frames, jobs, njobs);
-    return hipGetLastError();
+    return std::max(kRowsPerCountBlock * rowcarry_lds_bytes(g), agg_lds_bytes(g.TX, g.B));
 }
 
-hipError_t launch_rowcarry_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
-                                 int64_t nblocks, size_t lds_bytes, hipStream_t stream)
+hipError_t launch_count_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                              int64_t nblocks, size_t lds_bytes, hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rowcarry_batch_kernel, dim3((unsigned)nblocks), dim3(kRowThreads), (unsigned)lds_bytes,
-                       stream, frames, jobs, njobs);
+    const dim3 grid((unsigned)nblocks), block(kAggThreads);
+    if (TX == 32)
+        hipLaunchKernelGGL(count_batch_kernel<32>, grid, block, (unsigned)lds_bytes, stream, frames, jobs, njobs);
+    else if (TX == 128)
+        hipLaunchKernelGGL(count_batch_kernel<128>, grid, block, (unsigned)lds_bytes, stream, frames, jobs, njobs);
+    else
+        hipLaunchKernelGGL(count_batch_kernel<64>, grid, block, (unsigned)lds_bytes, stream, frames, jobs, njobs);
     return hipGetLastError();
 }
 

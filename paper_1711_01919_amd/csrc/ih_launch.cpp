@@ -15,8 +15,7 @@ size_t frame_scratch_words(const Geom& g) { return align_up(scratch_layout(g).wo
 int phase_of(const BatchLaunch& l)
 {
     switch (l.kind) {
-    case BatchLaunch::kRowCarry:
-    case BatchLaunch::kAgg: return 0;
+    case BatchLaunch::kCount: return 0;
     case BatchLaunch::kScanA:
     case BatchLaunch::kScanB: return 1;
     default: return 2;
@@ -60,37 +59,26 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
     std::vector<std::vector<Job>> tables;
     std::vector<BatchLaunch> launches;
 
-    {
+    // Count phase, one launch per tile width: per frame, row-carry blocks of
+    // four rows (jg_begin of the job holds their count), then one block per
+    // tile for the column counts.
+    for (int tx : {32, 64, 128}) {
         std::vector<Job> jobs;
         int64_t begin = 0;
         size_t lds = 0;
         for (size_t k = 0; k < n; ++k) {
-            jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
-            begin += frames[k].g.H;                       // one workgroup per row
-            lds = std::max(lds, rowcarry_lds(frames[k].g));
-        }
-        BatchLaunch l;
-        l.kind = BatchLaunch::kRowCarry;
-        l.lds = lds;
-        l.n = begin;
-        l.njobs = (int32_t)jobs.size();
-        launches.push_back(l);
-        tables.push_back(std::move(jobs));
-    }
-
-    for (int tx : {32, 64, 128}) {
-        std::vector<Job> jobs;
-        int64_t begin = 0;
-        for (size_t k = 0; k < n; ++k) {
             const Geom& g = frames[k].g;
             if (g.TX != tx) continue;
-            jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
-            begin += (int64_t)g.nTX * g.nTY;
+            const int32_t row_blocks = count_row_blocks(g);
+            jobs.push_back(Job{begin, (int32_t)k, row_blocks, 0, 0});
+            begin += row_blocks + (int64_t)g.nTX * g.nTY;
+            lds = std::max(lds, count_lds(g));
         }
         if (jobs.empty()) continue;
         BatchLaunch l;
-        l.kind = BatchLaunch::kAgg;
+        l.kind = BatchLaunch::kCount;
         l.tx = tx;
+        l.lds = lds;
         l.n = begin;
         l.njobs = (int32_t)jobs.size();
         launches.push_back(l);
@@ -166,8 +154,7 @@ hipError_t enqueue_batch(const BatchImage& img, const void* dev_image, int phase
         const Job* jobs = reinterpret_cast<const Job*>(base + l.jobs_off);
         hipError_t e = hipSuccess;
         switch (l.kind) {
-        case BatchLaunch::kRowCarry: e = launch_rowcarry_batch(fr, jobs, l.njobs, l.n, l.lds, s); break;
-        case BatchLaunch::kAgg: e = launch_agg_batch(l.tx, fr, jobs, l.njobs, l.n, s); break;
+        case BatchLaunch::kCount: e = launch_count_batch(l.tx, fr, jobs, l.njobs, l.n, l.lds, s); break;
         case BatchLaunch::kScanA: e = launch_scan_a_batch(fr, jobs, l.njobs, l.n, s); break;
         case BatchLaunch::kScanB: e = launch_scan_b_batch(fr, jobs, l.njobs, l.n, s); break;
         case BatchLaunch::kTile: e = launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid, s); break;

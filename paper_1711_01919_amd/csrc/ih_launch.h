@@ -11,14 +11,14 @@
 namespace ih {
 
 struct BatchLaunch {
-    enum Kind { kRowCarry, kAgg, kScanA, kScanB, kTile } kind = kAgg;
-    int tx = 64;               // kAgg: tile width of the frames it covers
+    enum Kind { kCount, kScanA, kScanB, kTile } kind = kCount;
+    int tx = 64;               // kCount: tile width of the frames it covers
     TileVariant v{};           // kTile: compiled kernel variant
     size_t jobs_off = 0;       // byte offset of this launch's job table in the image
     int32_t njobs = 0;
-    int64_t n = 0;             // blocks (kAgg, kScan*) or work items (kTile)
+    int64_t n = 0;             // blocks (kCount, kScan*) or work items (kTile)
     int32_t grid = 0;          // kTile: persistent workgroups
-    size_t lds = 0;            // kRowCarry: dynamic LDS bytes
+    size_t lds = 0;            // kCount: dynamic LDS bytes
 };
 
 struct BatchImage {
