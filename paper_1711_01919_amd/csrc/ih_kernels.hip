@@ -325,12 +325,12 @@ void count_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restr
 // ---------------------------------------------------------------------------
 // Phase 2: exclusive scans of the per-tile counts
 // ---------------------------------------------------------------------------
-// Exclusive scan of p[0], p[stride], ... p[(len-1)*stride] in place.  Loads of
-// a chunk are issued before its stores so that many are in flight at once.
-__device__ __forceinline__ void scan_seq(IH_GLOBAL uint32_t* p, int64_t stride, int len)
+// Exclusive scan of p[0], p[stride], ... p[(len-1)*stride] in place, starting
+// from `run`.  Loads of a chunk are issued before its stores so that many are
+// in flight at once.
+__device__ __forceinline__ void scan_seq(IH_GLOBAL uint32_t* p, int64_t stride, int len, uint32_t run)
 {
     constexpr int C = 16;
-    uint32_t run = 0;
     int k = 0;
     for (; k + C <= len; k += C) {
         uint32_t v[C];
@@ -346,57 +346,145 @@ __device__ __forceinline__ void scan_seq(IH_GLOBAL uint32_t* p, int64_t stride, 
     }
 }
 
-// Column counts across tile bands and tile totals across bands --
-// independent sequences, one thread each.
-__device__ __forceinline__ void scan_a_body(const FrameArgs& f, int64_t t)
+__device__ __forceinline__ uint32_t sum_seq(const IH_GLOBAL uint32_t* p, int64_t stride, int len)
 {
-    const Geom& g = f.g;
-    const int64_t B = g.B;
-    const int64_t ncol = (int64_t)g.W * B, ntot = (int64_t)g.nTX * B;
-    if (t < ncol) {
-        scan_seq(gmem(f.colc) + t, (int64_t)g.W * B, g.nTY);
-    } else if ((t -= ncol) < ntot) {
-        scan_seq(gmem(f.corner) + t, (int64_t)g.nTX * B, g.nTY);
+    constexpr int C = 16;
+    uint32_t s = 0;
+    int k = 0;
+    for (; k + C <= len; k += C) {
+        uint32_t v[C];
+#pragma unroll
+        for (int u = 0; u < C; ++u) v[u] = p[(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < C; ++u) s += v[u];
+    }
+    for (; k < len; ++k) s += p[k * stride];
+    return s;
+}
+
+// Sequences longer than one chunk are split over the four waves of a block:
+// each wave takes a quarter of every sequence of its block's 64, the part
+// totals meet in LDS, and each wave rescans its part from the total of the
+// parts before it.  The loads of a sequence then go out in one round instead
+// of one per chunk.  Shorter sequences take one thread each.
+constexpr int kScanParts = kScanThreads / kWave;
+
+__host__ __device__ inline int scan_parts(int len) { return len > 16 ? kScanParts : 1; }
+
+// Sequences covered by one scan block.
+__host__ __device__ inline int scan_per_block(int len) { return kScanThreads / scan_parts(len); }
+
+// p == nullptr: the thread has no sequence but still takes part in the
+// block's exchange (every thread of a block sees the same len).
+__device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t stride, int len, uint32_t* sums)
+{
+    const int P = scan_parts(len);
+    if (P == 1) {
+        if (p) scan_seq(p, stride, len, 0u);
+        return;
+    }
+    constexpr int C = 16;
+    const int part = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
+    const int lo = (int)((int64_t)len * part / P), hi = (int)((int64_t)len * (part + 1) / P);
+    const bool fits = hi - lo <= C;
+    uint32_t v[C];
+    uint32_t tot = 0;
+    if (p) {
+        if (fits) {
+#pragma unroll
+            for (int u = 0; u < C; ++u) v[u] = lo + u < hi ? p[(int64_t)(lo + u) * stride] : 0u;
+#pragma unroll
+            for (int u = 0; u < C; ++u) tot += v[u];
+        } else {
+            tot = sum_seq(p + (int64_t)lo * stride, stride, hi - lo);
+        }
+    }
+    sums[part * kWave + lane] = tot;
+    __syncthreads();
+    uint32_t run = 0;
+    for (int w = 0; w < part; ++w) run += sums[w * kWave + lane];
+    if (!p) return;
+    if (fits) {
+#pragma unroll
+        for (int u = 0; u < C; ++u)
+            if (lo + u < hi) {
+                p[(int64_t)(lo + u) * stride] = run;
+                run += v[u];
+            }
+    } else {
+        scan_seq(p + (int64_t)lo * stride, stride, hi - lo, run);
     }
 }
 
-// Band-scanned tile totals across tile columns: corner[i][j][b] becomes the
-// count of pixels above and to the left of tile (i, j).
-__device__ __forceinline__ void scan_b_body(const FrameArgs& f, int64_t t)
+// Column counts across tile bands and tile totals across bands --
+// independent sequences of length nTY.  `blk` is the block's index within
+// the frame's scan blocks.
+__device__ __forceinline__ void scan_a_body(const FrameArgs& f, int64_t blk, uint32_t* sums)
 {
     const Geom& g = f.g;
     const int64_t B = g.B;
-    if (t >= (int64_t)g.nTY * B) return;
-    const int64_t i = t / B, b = t - i * B;
-    scan_seq(gmem(f.corner) + i * g.nTX * B + b, B, g.nTX);
+    const int per = scan_per_block(g.nTY);
+    const int64_t t = blk * per + (int)threadIdx.x % per;
+    const int64_t ncol = (int64_t)g.W * B, ntot = (int64_t)g.nTX * B;
+    IH_GLOBAL uint32_t* p = nullptr;
+    int64_t stride = 0;
+    if (t < ncol) {
+        p = gmem(f.colc) + t;
+        stride = (int64_t)g.W * B;
+    } else if (t - ncol < ntot) {
+        p = gmem(f.corner) + (t - ncol);
+        stride = (int64_t)g.nTX * B;
+    }
+    scan_seq_parts(p, stride, g.nTY, sums);
+}
+
+// Band-scanned tile totals across tile columns (sequences of length nTX):
+// corner[i][j][b] becomes the count of pixels above and to the left of tile
+// (i, j).
+__device__ __forceinline__ void scan_b_body(const FrameArgs& f, int64_t blk, uint32_t* sums)
+{
+    const Geom& g = f.g;
+    const int64_t B = g.B;
+    const int per = scan_per_block(g.nTX);
+    const int64_t t = blk * per + (int)threadIdx.x % per;
+    IH_GLOBAL uint32_t* p = nullptr;
+    if (t < (int64_t)g.nTY * B) {
+        const int64_t i = t / B, b = t - i * B;
+        p = gmem(f.corner) + i * g.nTX * B + b;
+    }
+    scan_seq_parts(p, B, g.nTX, sums);
 }
 
 __global__ __launch_bounds__(kScanThreads)
 void scan_a_kernel(FrameArgs f)
 {
-    scan_a_body(f, (int64_t)blockIdx.x * kScanThreads + threadIdx.x);
+    __shared__ uint32_t sums[kScanThreads];
+    scan_a_body(f, blockIdx.x, sums);
 }
 
 __global__ __launch_bounds__(kScanThreads)
 void scan_b_kernel(FrameArgs f)
 {
-    scan_b_body(f, (int64_t)blockIdx.x * kScanThreads + threadIdx.x);
+    __shared__ uint32_t sums[kScanThreads];
+    scan_b_body(f, blockIdx.x, sums);
 }
 
 __global__ __launch_bounds__(kScanThreads)
 void scan_a_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
+    __shared__ uint32_t sums[kScanThreads];
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
-    scan_a_body(f, ((int64_t)blockIdx.x - jb.begin) * kScanThreads + threadIdx.x);
+    scan_a_body(f, (int64_t)blockIdx.x - jb.begin, sums);
 }
 
 __global__ __launch_bounds__(kScanThreads)
 void scan_b_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
+    __shared__ uint32_t sums[kScanThreads];
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
-    scan_b_body(f, ((int64_t)blockIdx.x - jb.begin) * kScanThreads + threadIdx.x);
+    scan_b_body(f, (int64_t)blockIdx.x - jb.begin, sums);
 }
 
 // ---------------------------------------------------------------------------
@@ -924,13 +1012,14 @@ static TileFns tile_fns(const TileVariant& v)
 
 int64_t scan_a_blocks(const Geom& g)
 {
-    const int64_t n = (int64_t)g.W * g.B + (int64_t)g.nTX * g.B;
-    return (n + kScanThreads - 1) / kScanThreads;
+    const int64_t n = (int64_t)g.W * g.B + (int64_t)g.nTX * g.B, per = scan_per_block(g.nTY);
+    return (n + per - 1) / per;
 }
 
 int64_t scan_b_blocks(const Geom& g)
 {
-    return ((int64_t)g.nTY * g.B + kScanThreads - 1) / kScanThreads;
+    const int64_t per = scan_per_block(g.nTX);
+    return ((int64_t)g.nTY * g.B + per - 1) / per;
 }
 
 hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStream_t stream)
