@@ -63,6 +63,23 @@ def test_every_tile_candidate(ihb, orc, tx, ty, nt):
     plan.close()
 
 
+def test_small_and_large_tile_grids(ihb, orc):
+    """One batch with tile grids of 1 x 2, 38 x 22 and 138 x 66 tiles: carry
+    sequences shorter and longer than one scan chunk, split over the waves of
+    a scan block or not."""
+    rng = np.random.default_rng(77)
+    shapes = [(600, 700, 8), (2200, 2100, 4), (16, 33, 5)]   # grids 38x22, 138x66, 1x2 at 32x16
+    frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _ in shapes]
+    bins = [b for _, _, b in shapes]
+    fr, outs = to_dev(frames, bins)
+    plan = ihb.BatchPlan(fr, outs, bins, tile=(32, 16))
+    plan.launch()
+    torch.cuda.synchronize()
+    for k, (f, b) in enumerate(zip(frames, bins)):
+        assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(f, b)), (k, f.shape, b)
+    plan.close()
+
+
 def test_graph_replays_with_eager_work_between(ihb, orc):
     rng = np.random.default_rng(21)
     frames = [rng.integers(0, 256, size=(240, 320), dtype=np.uint8) for _ in range(5)]
