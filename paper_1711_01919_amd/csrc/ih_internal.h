@@ -103,9 +103,10 @@ hipError_t launch_count_batch(int TX, const FrameArgs* frames, const Job* jobs, 
 // Row-carry blocks (four rows each) and dynamic LDS bytes of a frame's count phase.
 int32_t count_row_blocks(const Geom& g);
 size_t count_lds(const Geom& g);
-hipError_t launch_scan_a_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+// `parts` is scan_parts() of every frame the launch covers.
+hipError_t launch_scan_a_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
                                int64_t nblocks, hipStream_t stream);
-hipError_t launch_scan_b_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+hipError_t launch_scan_b_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
                                int64_t nblocks, hipStream_t stream);
 // Persistent tile launch: `grid` workgroups loop over `nitems` work items.
 hipError_t launch_tile_batch(const TileVariant& v, const FrameArgs* frames, const Job* jobs,
@@ -114,6 +115,12 @@ hipError_t launch_tile_batch(const TileVariant& v, const FrameArgs* frames, cons
 int32_t tile_resident_blocks(const TileVariant& v);
 
 // Blocks of the scan kernels for one frame.
+// Carry sequences longer than one 16-element chunk are split over the
+// kScanParts waves of a scan block; shorter ones take one thread each.
+// scan_a's sequences run over the nTY bands, scan_b's over the nTX tile columns.
+constexpr int kScanParts = kScanThreads / kWave;
+inline int scan_parts(int len) { return len > 16 ? kScanParts : 1; }
+inline int scan_per_block(int len) { return kScanThreads / scan_parts(len); }
 int64_t scan_a_blocks(const Geom& g);
 int64_t scan_b_blocks(const Geom& g);
 

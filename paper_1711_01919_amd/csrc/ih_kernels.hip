@@ -367,20 +367,18 @@ __device__ __forceinline__ uint32_t sum_seq(const IH_GLOBAL uint32_t* p, int64_t
 // totals meet in LDS, and each wave rescans its part from the total of the
 // parts before it.  The loads of a sequence then go out in one round instead
 // of one per chunk.  Shorter sequences take one thread each.
-constexpr int kScanParts = kScanThreads / kWave;
 
-__host__ __device__ inline int scan_parts(int len) { return len > 16 ? kScanParts : 1; }
-
-// Sequences covered by one scan block.
-__host__ __device__ inline int scan_per_block(int len) { return kScanThreads / scan_parts(len); }
-
-// p == nullptr: the thread has no sequence but still takes part in the
-// block's exchange (every thread of a block sees the same len).
-__device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t stride, int len, uint32_t* sums)
+// P is scan_parts(len) (each kernel is compiled for one of the two forms, so
+// the one-thread form keeps its small register footprint).  active == false:
+// the thread has no sequence but still takes part in the block's exchange
+// (every thread of a block sees the same len).  `stride` is the same for the
+// whole block, so address arithmetic stays scalar.
+template <int P>
+__device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t stride, int len, bool active,
+                                               uint32_t* sums)
 {
-    const int P = scan_parts(len);
-    if (P == 1) {
-        if (p) scan_seq(p, stride, len, 0u);
+    if constexpr (P == 1) {
+        if (active) scan_seq(p, stride, len, 0u);
         return;
     }
     constexpr int C = 16;
@@ -389,7 +387,7 @@ __device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t st
     const bool fits = hi - lo <= C;
     uint32_t v[C];
     uint32_t tot = 0;
-    if (p) {
+    if (active) {
         if (fits) {
 #pragma unroll
             for (int u = 0; u < C; ++u) v[u] = lo + u < hi ? p[(int64_t)(lo + u) * stride] : 0u;
@@ -403,7 +401,7 @@ __device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t st
     __syncthreads();
     uint32_t run = 0;
     for (int w = 0; w < part; ++w) run += sums[w * kWave + lane];
-    if (!p) return;
+    if (!active) return;
     if (fits) {
 #pragma unroll
         for (int u = 0; u < C; ++u)
@@ -417,74 +415,73 @@ __device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t st
 }
 
 // Column counts across tile bands and tile totals across bands --
-// independent sequences of length nTY.  `blk` is the block's index within
-// the frame's scan blocks.
+// independent sequences of length nTY; the frame's blocks take the column
+// sequences first, then the tile-total ones, so that each block holds one
+// kind.  `blk` is the block's index within the frame's scan blocks.
+template <int P>
 __device__ __forceinline__ void scan_a_body(const FrameArgs& f, int64_t blk, uint32_t* sums)
 {
     const Geom& g = f.g;
     const int64_t B = g.B;
-    const int per = scan_per_block(g.nTY);
-    const int64_t t = blk * per + (int)threadIdx.x % per;
+    constexpr int per = kScanThreads / P;
     const int64_t ncol = (int64_t)g.W * B, ntot = (int64_t)g.nTX * B;
-    IH_GLOBAL uint32_t* p = nullptr;
-    int64_t stride = 0;
-    if (t < ncol) {
-        p = gmem(f.colc) + t;
-        stride = (int64_t)g.W * B;
-    } else if (t - ncol < ntot) {
-        p = gmem(f.corner) + (t - ncol);
-        stride = (int64_t)g.nTX * B;
-    }
-    scan_seq_parts(p, stride, g.nTY, sums);
+    const int64_t col_blocks = (ncol + per - 1) / per;
+    const bool is_col = blk < col_blocks;                    // uniform over the block
+    const int64_t t = (is_col ? blk : blk - col_blocks) * per + (int)threadIdx.x % per;
+    IH_GLOBAL uint32_t* base = is_col ? gmem(f.colc) : gmem(f.corner);
+    const int64_t stride = (is_col ? (int64_t)g.W : (int64_t)g.nTX) * B;
+    scan_seq_parts<P>(base + t, stride, g.nTY, t < (is_col ? ncol : ntot), sums);
 }
 
 // Band-scanned tile totals across tile columns (sequences of length nTX):
 // corner[i][j][b] becomes the count of pixels above and to the left of tile
 // (i, j).
+template <int P>
 __device__ __forceinline__ void scan_b_body(const FrameArgs& f, int64_t blk, uint32_t* sums)
 {
     const Geom& g = f.g;
     const int64_t B = g.B;
-    const int per = scan_per_block(g.nTX);
+    constexpr int per = kScanThreads / P;
     const int64_t t = blk * per + (int)threadIdx.x % per;
-    IH_GLOBAL uint32_t* p = nullptr;
-    if (t < (int64_t)g.nTY * B) {
-        const int64_t i = t / B, b = t - i * B;
-        p = gmem(f.corner) + i * g.nTX * B + b;
-    }
-    scan_seq_parts(p, B, g.nTX, sums);
+    const bool active = t < (int64_t)g.nTY * B;
+    const int64_t i = t / B, b = t - i * B;
+    scan_seq_parts<P>(gmem(f.corner) + i * g.nTX * B + b, B, g.nTX, active, sums);
 }
 
+template <int P>
 __global__ __launch_bounds__(kScanThreads)
 void scan_a_kernel(FrameArgs f)
 {
-    __shared__ uint32_t sums[kScanThreads];
-    scan_a_body(f, blockIdx.x, sums);
+    __shared__ uint32_t sums[P == 1 ? 1 : kScanThreads];
+    scan_a_body<P>(f, blockIdx.x, sums);
 }
 
+template <int P>
 __global__ __launch_bounds__(kScanThreads)
 void scan_b_kernel(FrameArgs f)
 {
-    __shared__ uint32_t sums[kScanThreads];
-    scan_b_body(f, blockIdx.x, sums);
+    __shared__ uint32_t sums[P == 1 ? 1 : kScanThreads];
+    scan_b_body<P>(f, blockIdx.x, sums);
 }
 
+template <int P>
 __global__ __launch_bounds__(kScanThreads)
 void scan_a_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
-    __shared__ uint32_t sums[kScanThreads];
+    __shared__ uint32_t sums[P == 1 ? 1 : kScanThreads];
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
-    scan_a_body(f, (int64_t)blockIdx.x - jb.begin, sums);
+    scan_a_body<P>(f, (int64_t)blockIdx.x - jb.begin, sums);
 }
 
+template <int P>
 __global__ __launch_bounds__(kScanThreads)
 void scan_b_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
-    __shared__ uint32_t sums[kScanThreads];
+    __shared__ uint32_t sums[P == 1 ? 1 : kScanThreads];
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
-    scan_b_body(f, (int64_t)blockIdx.x - jb.begin, sums);
+    scan_b_body<P>(f, (int64_t)blockIdx.x - jb.begin, sums);
 }
 
 // ---------------------------------------------------------------------------
@@ -1012,8 +1009,8 @@ static TileFns tile_fns(const TileVariant& v)
 
 int64_t scan_a_blocks(const Geom& g)
 {
-    const int64_t n = (int64_t)g.W * g.B + (int64_t)g.nTX * g.B, per = scan_per_block(g.nTY);
-    return (n + per - 1) / per;
+    const int64_t per = scan_per_block(g.nTY);
+    return ((int64_t)g.W * g.B + per - 1) / per + ((int64_t)g.nTX * g.B + per - 1) / per;
 }
 
 int64_t scan_b_blocks(const Geom& g)
@@ -1039,8 +1036,16 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
         break;
     }
     case Phase::kScan:
-        hipLaunchKernelGGL(scan_a_kernel, dim3((unsigned)scan_a_blocks(g)), dim3(kScanThreads), 0, stream, f);
-        hipLaunchKernelGGL(scan_b_kernel, dim3((unsigned)scan_b_blocks(g)), dim3(kScanThreads), 0, stream, f);
+        if (scan_parts(g.nTY) == 1)
+            hipLaunchKernelGGL(scan_a_kernel<1>, dim3((unsigned)scan_a_blocks(g)), dim3(kScanThreads), 0, stream, f);
+        else
+            hipLaunchKernelGGL(scan_a_kernel<kScanParts>, dim3((unsigned)scan_a_blocks(g)), dim3(kScanThreads), 0,
+                               stream, f);
+        if (scan_parts(g.nTX) == 1)
+            hipLaunchKernelGGL(scan_b_kernel<1>, dim3((unsigned)scan_b_blocks(g)), dim3(kScanThreads), 0, stream, f);
+        else
+            hipLaunchKernelGGL(scan_b_kernel<kScanParts>, dim3((unsigned)scan_b_blocks(g)), dim3(kScanThreads), 0,
+                               stream, f);
         break;
     case Phase::kTile: {
         const int32_t n_int = interior_groups(g, f.frame, f.out);
@@ -1084,21 +1089,27 @@ hipError_t launch_count_batch(int TX, const FrameArgs* frames, const Job* jobs, 
     return hipGetLastError();
 }
 
-hipError_t launch_scan_a_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+hipError_t launch_scan_a_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
                                int64_t nblocks, hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scan_a_batch_kernel, dim3((unsigned)nblocks), dim3(kScanThreads), 0, stream,
-                       frames, jobs, njobs);
+    const dim3 grid((unsigned)nblocks), block(kScanThreads);
+    if (parts == 1)
+        hipLaunchKernelGGL(scan_a_batch_kernel<1>, grid, block, 0, stream, frames, jobs, njobs);
+    else
+        hipLaunchKernelGGL(scan_a_batch_kernel<kScanParts>, grid, block, 0, stream, frames, jobs, njobs);
     return hipGetLastError();
 }
 
-hipError_t launch_scan_b_batch(const FrameArgs* frames, const Job* jobs, int32_t njobs,
+hipError_t launch_scan_b_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
                                int64_t nblocks, hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scan_b_batch_kernel, dim3((unsigned)nblocks), dim3(kScanThreads), 0, stream,
-                       frames, jobs, njobs);
+    const dim3 grid((unsigned)nblocks), block(kScanThreads);
+    if (parts == 1)
+        hipLaunchKernelGGL(scan_b_batch_kernel<1>, grid, block, 0, stream, frames, jobs, njobs);
+    else
+        hipLaunchKernelGGL(scan_b_batch_kernel<kScanParts>, grid, block, 0, stream, frames, jobs, njobs);
     return hipGetLastError();
 }
 

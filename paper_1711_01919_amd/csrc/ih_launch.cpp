@@ -84,11 +84,16 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         launches.push_back(l);
         tables.push_back(std::move(jobs));
     }
-    for (BatchLaunch::Kind kind : {BatchLaunch::kScanA, BatchLaunch::kScanB}) {
+    // Scans: one launch per kind and per scan form (one thread per carry
+    // sequence, or sequences split over the waves of a block).
+    for (BatchLaunch::Kind kind : {BatchLaunch::kScanA, BatchLaunch::kScanB})
+    for (int parts : {1, kScanParts}) {
         std::vector<Job> jobs;
         int64_t begin = 0;
         for (size_t k = 0; k < n; ++k) {
-            const int64_t nb = kind == BatchLaunch::kScanA ? scan_a_blocks(frames[k].g) : scan_b_blocks(frames[k].g);
+            const Geom& g = frames[k].g;
+            if (scan_parts(kind == BatchLaunch::kScanA ? g.nTY : g.nTX) != parts) continue;
+            const int64_t nb = kind == BatchLaunch::kScanA ? scan_a_blocks(g) : scan_b_blocks(g);
             if (nb == 0) continue;
             jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
             begin += nb;
@@ -96,6 +101,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         if (jobs.empty()) continue;
         BatchLaunch l;
         l.kind = kind;
+        l.parts = parts;
         l.n = begin;
         l.njobs = (int32_t)jobs.size();
         launches.push_back(l);
@@ -155,8 +161,8 @@ hipError_t enqueue_batch(const BatchImage& img, const void* dev_image, int phase
         hipError_t e = hipSuccess;
         switch (l.kind) {
         case BatchLaunch::kCount: e = launch_count_batch(l.tx, fr, jobs, l.njobs, l.n, l.lds, s); break;
-        case BatchLaunch::kScanA: e = launch_scan_a_batch(fr, jobs, l.njobs, l.n, s); break;
-        case BatchLaunch::kScanB: e = launch_scan_b_batch(fr, jobs, l.njobs, l.n, s); break;
+        case BatchLaunch::kScanA: e = launch_scan_a_batch(l.parts, fr, jobs, l.njobs, l.n, s); break;
+        case BatchLaunch::kScanB: e = launch_scan_b_batch(l.parts, fr, jobs, l.njobs, l.n, s); break;
         case BatchLaunch::kTile: e = launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid, s); break;
         }
         if (e != hipSuccess) return e;

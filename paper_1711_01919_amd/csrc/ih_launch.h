@@ -13,6 +13,7 @@ namespace ih {
 struct BatchLaunch {
     enum Kind { kCount, kScanA, kScanB, kTile } kind = kCount;
     int tx = 64;               // kCount: tile width of the frames it covers
+    int parts = 1;             // kScanA, kScanB: scan form (scan_parts of its frames)
     TileVariant v{};           // kTile: compiled kernel variant
     size_t jobs_off = 0;       // byte offset of this launch's job table in the image
     int32_t njobs = 0;
