@@ -210,8 +210,23 @@ def plain_and_query_legs(torch, ihb, synth, stream) -> dict:
         fn()
         ms1 = timed(torch, stream, fn, 50) / 50
         forms[name] = {"ms_per_frame": ms1, "hbm_frac": by1 / (ms1 / 1e3) / 1e9 / HBM_PEAK_GBS}
+    # region queries on both layouts: 1e5 rectangles (seed 8, drawn as for the
+    # 640x480 frame) already on the device
+    qr = np.random.default_rng(8)
+    nq = 100_000
+    xs = np.sort(qr.integers(0, W1, size=(nq, 2)), axis=1)
+    ys = np.sort(qr.integers(0, H1, size=(nq, 2)), axis=1)
+    rd1 = torch.from_numpy(np.stack([xs[:, 0], ys[:, 0], xs[:, 1], ys[:, 1]], axis=1).astype(np.int32)).cuda()
+    h1 = torch.empty((nq, B1), dtype=torch.uint32, device="cuda")
+    for name, comp, query, shape in (("hwb", ihb.compute, ihb.query_device, (H1, W1, B1)),
+                                     ("binmajor", ihb.compute_binmajor, ihb.query_binmajor_device, (B1, H1, W1))):
+        comp(f1, B1, out=o1, stream=stream)
+        ihv = o1.view(*shape)
+        query(ihv, rd1, out=h1, stream=stream)
+        qms = timed(torch, stream, lambda: query(ihv, rd1, out=h1, stream=stream), 20) / 20
+        forms[name].update({"query_1e5_rects_ms": qms, "rects_per_s": nq / (qms / 1e3)})
     out["single_frame_1920x1080_B64_forms"] = forms
-    del f1, o1
+    del f1, o1, rd1, h1
     I, B, rects = synth.mixture_frame()
     H, W = I.shape
     f = torch.from_numpy(I).cuda()

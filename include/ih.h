@@ -57,7 +57,8 @@ typedef struct {
 
 /* A non-owning view of an integral histogram already in device memory. */
 typedef struct {
-    const uint32_t* data;       /* device, H*W*B uint32 in the layout above */
+    const uint32_t* data;       /* device, H*W*B uint32 in the layout above
+                                   (bin-major for the *_binmajor queries)   */
     int32_t H, W, B;
     ih_stream_t stream;         /* stream the query work is enqueued on      */
 } ih_view;
@@ -85,8 +86,8 @@ ih_status ih_compute(const uint8_t* frame, int32_t H, int32_t W, int32_t B,
  * ih_compute_binmajor -- as ih_compute, with the result in the paper's
  * bin-major layout b x h x w (Sec. 3.1, Fig. 2): entry (x, y, b) at
  * out[(b*H + y)*W + x], so every bin is one contiguous H x W plane.  Same
- * arguments, errors and scratch as ih_compute; ih_query expects the
- * H x W x B layout and does not read this one.
+ * arguments, errors and scratch as ih_compute.  ih_query reads the
+ * H x W x B layout only; ih_query_binmajor reads this one.
  */
 ih_status ih_compute_binmajor(const uint8_t* frame, int32_t H, int32_t W, int32_t B, uint32_t* out,
                               ih_stream_t stream);
@@ -131,6 +132,19 @@ ih_status ih_query(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* 
  */
 ih_status ih_query_device(const ih_view* ih, const ih_rect* rects_dev, size_t n,
                           uint32_t* hists, uint32_t* bad_count);
+
+/*
+ * ih_query_binmajor, ih_query_binmajor_device -- as ih_query and
+ * ih_query_device (Eq. 2), on an integral histogram in the bin-major layout
+ * of ih_compute_binmajor: ih->data holds B planes of H x W uint32, entry
+ * (x, y, b) at (b*H + y)*W + x.  Rectangles, validation, errors, the result
+ * layout (hists[r*B + b]) and the stream are those of the H x W x B calls.
+ * Each bin's four corners lie in its own plane, so a rectangle costs 4*B
+ * scattered reads instead of four runs of B contiguous values.
+ */
+ih_status ih_query_binmajor(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* hists);
+ih_status ih_query_binmajor_device(const ih_view* ih, const ih_rect* rects_dev, size_t n,
+                                   uint32_t* hists, uint32_t* bad_count);
 
 /* ---------------------------------------------------------------------------
  * Batched form: many frames of uneven size and bin count, one launch per

@@ -93,7 +93,10 @@ def _load() -> ctypes.CDLL:
     lib.ih_compute_lut.restype = ctypes.c_int
     lib.ih_query.argtypes = [ctypes.POINTER(View), vp, sz, vp]
     lib.ih_query_device.argtypes = [ctypes.POINTER(View), vp, sz, vp, vp]
-    for f in (lib.ih_compute, lib.ih_query, lib.ih_query_device):
+    lib.ih_query_binmajor.argtypes = [ctypes.POINTER(View), vp, sz, vp]
+    lib.ih_query_binmajor_device.argtypes = [ctypes.POINTER(View), vp, sz, vp, vp]
+    for f in (lib.ih_compute, lib.ih_query, lib.ih_query_device, lib.ih_query_binmajor,
+              lib.ih_query_binmajor_device):
         f.restype = ctypes.c_int
     lib.ih_profile_enable.argtypes = [ctypes.c_int]
     lib.ih_profile_enable.restype = ctypes.c_int
@@ -230,6 +233,39 @@ def query_device(ih: torch.Tensor, rects_dev: torch.Tensor, out: torch.Tensor | 
         out = torch.empty((n, ih.shape[2]), dtype=torch.uint32, device=ih.device)
     _check(lib.ih_query_device(ctypes.byref(v), _ptr(rects_dev), n, _ptr(out), _ptr(bad_count)),
            "ih_query_device")
+    return out
+
+
+def _view_binmajor(ih: torch.Tensor, stream) -> View:
+    if ih.dtype != torch.uint32 or ih.dim() != 3 or not ih.is_cuda or not ih.is_contiguous():
+        raise ValueError("ih must be a contiguous (B, H, W) uint32 CUDA tensor")
+    B, H, W = ih.shape
+    return View(_ptr(ih), H, W, B, _stream_handle(stream))
+
+
+def query_binmajor(ih: torch.Tensor, rects, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """ih_query_binmajor: region histograms (n, B) from a bin-major (B, H, W)
+    integral histogram, for host rectangles {x0, y0, x1, y1} (inclusive)."""
+    rects = np.ascontiguousarray(rects, dtype=np.int32).reshape(-1, 4)
+    v = _view_binmajor(ih, stream)
+    n = rects.shape[0]
+    if out is None:
+        out = torch.empty((n, ih.shape[0]), dtype=torch.uint32, device=ih.device)
+    _check(lib.ih_query_binmajor(ctypes.byref(v), rects.ctypes.data, n, _ptr(out)), "ih_query_binmajor")
+    return out
+
+
+def query_binmajor_device(ih: torch.Tensor, rects_dev: torch.Tensor, out: torch.Tensor | None = None,
+                          bad_count: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """ih_query_binmajor_device: as query_binmajor, rectangles on the device."""
+    if rects_dev.dtype != torch.int32 or not rects_dev.is_cuda or not rects_dev.is_contiguous():
+        raise ValueError("rects_dev must be a contiguous int32 CUDA tensor of shape (n, 4)")
+    v = _view_binmajor(ih, stream)
+    n = rects_dev.numel() // 4
+    if out is None:
+        out = torch.empty((n, ih.shape[0]), dtype=torch.uint32, device=ih.device)
+    _check(lib.ih_query_binmajor_device(ctypes.byref(v), _ptr(rects_dev), n, _ptr(out), _ptr(bad_count)),
+           "ih_query_binmajor_device")
     return out
 
 

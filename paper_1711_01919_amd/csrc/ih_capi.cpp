@@ -83,6 +83,54 @@ ih_status check_view(const ih_view* ih)
     return ih::check_shape(ih->H, ih->W, ih->B);
 }
 
+// Region queries (Eq. 2) on either layout: host rectangles are validated on
+// the host and staged through stream-ordered device memory; device
+// rectangles are checked by the kernel.
+ih_status query_host(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* hists, bool binmajor)
+{
+    if (ih_status st = check_view(ih)) return st;
+    if (n == 0) return IH_OK;
+    if (!rects || !hists) return fail(IH_ERR_INVALID_ARG, "rects and hists must be non-null");
+    if (n > (size_t)INT64_MAX / 256) return fail(IH_ERR_RANGE, "too many rectangles");
+    for (size_t r = 0; r < n; ++r) {
+        const ih_rect& q = rects[r];
+        if (q.x0 < 0 || q.x0 > q.x1 || q.x1 >= ih->W || q.y0 < 0 || q.y0 > q.y1 || q.y1 >= ih->H)
+            return fail(IH_ERR_INVALID_ARG, "rectangle %zu {%d,%d,%d,%d} is outside the %dx%d frame",
+                        r, q.x0, q.y0, q.x1, q.y1, ih->W, ih->H);
+    }
+    hipStream_t s = static_cast<hipStream_t>(ih->stream);
+    void* d = nullptr;
+    hipError_t e = hipMallocAsync(&d, n * sizeof(ih_rect), s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(IH_ERR_OOM, "hipMallocAsync for %zu rectangles: %s", n, hipGetErrorString(e));
+    }
+    // Pageable source: the copy is staged before the call returns, so the
+    // caller may reuse rects at once.
+    e = hipMemcpyAsync(d, rects, n * sizeof(ih_rect), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = ih::launch_query(ih->data, ih->H, ih->W, ih->B, static_cast<const int32_t*>(d),
+                             (int64_t)n, hists, nullptr, binmajor, s);
+    hipError_t e2 = hipFreeAsync(d, s);
+    if (e != hipSuccess) return hip_fail(e, "query");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    return IH_OK;
+}
+
+ih_status query_dev(const ih_view* ih, const ih_rect* rects_dev, size_t n, uint32_t* hists,
+                    uint32_t* bad_count, bool binmajor)
+{
+    if (ih_status st = check_view(ih)) return st;
+    if (n == 0) return IH_OK;
+    if (!rects_dev || !hists) return fail(IH_ERR_INVALID_ARG, "rects and hists must be non-null");
+    if (n > (size_t)INT64_MAX / 256) return fail(IH_ERR_RANGE, "too many rectangles");
+    hipError_t e = ih::launch_query(ih->data, ih->H, ih->W, ih->B,
+                                    reinterpret_cast<const int32_t*>(rects_dev), (int64_t)n, hists,
+                                    bad_count, binmajor, static_cast<hipStream_t>(ih->stream));
+    if (e != hipSuccess) return hip_fail(e, "query");
+    return IH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -173,47 +221,24 @@ ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, 
 
 ih_status ih_query(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* hists)
 {
-    if (ih_status st = check_view(ih)) return st;
-    if (n == 0) return IH_OK;
-    if (!rects || !hists) return fail(IH_ERR_INVALID_ARG, "rects and hists must be non-null");
-    if (n > (size_t)INT64_MAX / 256) return fail(IH_ERR_RANGE, "too many rectangles");
-    for (size_t r = 0; r < n; ++r) {
-        const ih_rect& q = rects[r];
-        if (q.x0 < 0 || q.x0 > q.x1 || q.x1 >= ih->W || q.y0 < 0 || q.y0 > q.y1 || q.y1 >= ih->H)
-            return fail(IH_ERR_INVALID_ARG, "rectangle %zu {%d,%d,%d,%d} is outside the %dx%d frame",
-                        r, q.x0, q.y0, q.x1, q.y1, ih->W, ih->H);
-    }
-    hipStream_t s = static_cast<hipStream_t>(ih->stream);
-    void* d = nullptr;
-    hipError_t e = hipMallocAsync(&d, n * sizeof(ih_rect), s);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(IH_ERR_OOM, "hipMallocAsync for %zu rectangles: %s", n, hipGetErrorString(e));
-    }
-    // Pageable source: the copy is staged before the call returns, so the
-    // caller may reuse rects at once.
-    e = hipMemcpyAsync(d, rects, n * sizeof(ih_rect), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = ih::launch_query(ih->data, ih->H, ih->W, ih->B, static_cast<const int32_t*>(d),
-                             (int64_t)n, hists, nullptr, s);
-    hipError_t e2 = hipFreeAsync(d, s);
-    if (e != hipSuccess) return hip_fail(e, "query");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
-    return IH_OK;
+    return query_host(ih, rects, n, hists, false);
 }
 
 ih_status ih_query_device(const ih_view* ih, const ih_rect* rects_dev, size_t n,
                           uint32_t* hists, uint32_t* bad_count)
 {
-    if (ih_status st = check_view(ih)) return st;
-    if (n == 0) return IH_OK;
-    if (!rects_dev || !hists) return fail(IH_ERR_INVALID_ARG, "rects and hists must be non-null");
-    if (n > (size_t)INT64_MAX / 256) return fail(IH_ERR_RANGE, "too many rectangles");
-    hipError_t e = ih::launch_query(ih->data, ih->H, ih->W, ih->B,
-                                    reinterpret_cast<const int32_t*>(rects_dev), (int64_t)n, hists,
-                                    bad_count, static_cast<hipStream_t>(ih->stream));
-    if (e != hipSuccess) return hip_fail(e, "query");
-    return IH_OK;
+    return query_dev(ih, rects_dev, n, hists, bad_count, false);
+}
+
+ih_status ih_query_binmajor(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* hists)
+{
+    return query_host(ih, rects, n, hists, true);
+}
+
+ih_status ih_query_binmajor_device(const ih_view* ih, const ih_rect* rects_dev, size_t n,
+                                   uint32_t* hists, uint32_t* bad_count)
+{
+    return query_dev(ih, rects_dev, n, hists, bad_count, true);
 }
 
 }  // extern "C"

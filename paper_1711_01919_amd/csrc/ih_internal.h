@@ -133,8 +133,9 @@ hipError_t launch_tile_bm(const FrameArgs& f, hipStream_t stream);
 hipError_t launch_lut_store(const uint8_t* lut_host, uint32_t* dst, hipStream_t stream);
 
 // ---- region query ---------------------------------------------------------
+// binmajor: ih holds the b x h x w layout instead of H x W x B.
 hipError_t launch_query(const uint32_t* ih, int32_t H, int32_t W, int32_t B,
                         const int32_t* rects, int64_t n, uint32_t* hists,
-                        uint32_t* bad_count, hipStream_t stream);
+                        uint32_t* bad_count, bool binmajor, hipStream_t stream);
 
 }  // namespace ih

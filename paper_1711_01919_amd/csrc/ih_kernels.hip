@@ -788,20 +788,29 @@ void tile_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restri
 // corner across the lanes -- and writes h(R, b).
 constexpr int kQueryThreads = 256;
 
-__device__ __forceinline__ uint32_t four_corners(const IH_GLOBAL uint32_t* ih, int32_t W, int32_t B,
+// Index of entry (x, y, b): bins innermost (H x W x B), or, with BM, the
+// bin-major b x h x w layout, where the four corners of a bin lie in its own
+// H x W plane (scattered 4-byte gathers instead of B contiguous values).
+template <bool BM>
+__device__ __forceinline__ size_t entry(int32_t H, int32_t W, int32_t B, int32_t x, int32_t y, int b)
+{
+    return BM ? ((size_t)b * H + y) * W + x : ((size_t)y * W + x) * B + b;
+}
+
+template <bool BM>
+__device__ __forceinline__ uint32_t four_corners(const IH_GLOBAL uint32_t* ih, int32_t H, int32_t W, int32_t B,
                                                  int32_t x0, int32_t y0, int32_t x1, int32_t y1, int b)
 {
-    const size_t rowA = (size_t)y1 * W;                   // row y1
-    uint32_t h = ih[(rowA + x1) * B + b];
-    if (x0 > 0) h -= ih[(rowA + x0 - 1) * B + b];
+    uint32_t h = ih[entry<BM>(H, W, B, x1, y1, b)];
+    if (x0 > 0) h -= ih[entry<BM>(H, W, B, x0 - 1, y1, b)];
     if (y0 > 0) {
-        const size_t rowB = (size_t)(y0 - 1) * W;          // row y0-1
-        h -= ih[(rowB + x1) * B + b];
-        if (x0 > 0) h += ih[(rowB + x0 - 1) * B + b];
+        h -= ih[entry<BM>(H, W, B, x1, y0 - 1, b)];
+        if (x0 > 0) h += ih[entry<BM>(H, W, B, x0 - 1, y0 - 1, b)];
     }
     return h;
 }
 
+template <bool BM>
 __global__ __launch_bounds__(kQueryThreads)
 void query_kernel(const uint32_t* __restrict__ ih_, int32_t H, int32_t W, int32_t B,
                   const int32_t* __restrict__ rects, int64_t n,
@@ -819,7 +828,7 @@ void query_kernel(const uint32_t* __restrict__ ih_, int32_t H, int32_t W, int32_
         const bool ok = x0 >= 0 && x0 <= x1 && x1 < W && y0 >= 0 && y0 <= y1 && y1 < H;
         if (!ok && lane == 0 && bad) atomicAdd(bad, 1u);
         for (int b = lane; b < B; b += kWave)
-            hists[r * B + b] = ok ? four_corners(ih, W, B, x0, y0, x1, y1, b) : 0u;
+            hists[r * B + b] = ok ? four_corners<BM>(ih, H, W, B, x0, y0, x1, y1, b) : 0u;
     } else {
         const int per = kWave / B;                            // rectangles per wave
         const int sub = lane / B;
@@ -830,7 +839,7 @@ void query_kernel(const uint32_t* __restrict__ ih_, int32_t H, int32_t W, int32_
         const int32_t x0 = rc[0], y0 = rc[1], x1 = rc[2], y1 = rc[3];
         const bool ok = x0 >= 0 && x0 <= x1 && x1 < W && y0 >= 0 && y0 <= y1 && y1 < H;
         if (!ok && b == 0 && bad) atomicAdd(bad, 1u);
-        hists[r * B + b] = ok ? four_corners(ih, W, B, x0, y0, x1, y1, b) : 0u;
+        hists[r * B + b] = ok ? four_corners<BM>(ih, H, W, B, x0, y0, x1, y1, b) : 0u;
     }
 }
 
@@ -1173,14 +1182,18 @@ hipError_t launch_lut_store(const uint8_t* lut_host, uint32_t* dst, hipStream_t 
 
 hipError_t launch_query(const uint32_t* ih, int32_t H, int32_t W, int32_t B,
                         const int32_t* rects, int64_t n, uint32_t* hists,
-                        uint32_t* bad_count, hipStream_t stream)
+                        uint32_t* bad_count, bool binmajor, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
     const int64_t per = B >= kWave ? 1 : kWave / B;           // rectangles per wave
     const int64_t waves = (n + per - 1) / per;
     const int64_t blocks = (waves + kQueryThreads / kWave - 1) / (kQueryThreads / kWave);
-    hipLaunchKernelGGL(query_kernel, dim3((unsigned)blocks), dim3(kQueryThreads), 0, stream,
-                       ih, H, W, B, rects, n, hists, bad_count);
+    if (binmajor)
+        hipLaunchKernelGGL(query_kernel<true>, dim3((unsigned)blocks), dim3(kQueryThreads), 0, stream,
+                           ih, H, W, B, rects, n, hists, bad_count);
+    else
+        hipLaunchKernelGGL(query_kernel<false>, dim3((unsigned)blocks), dim3(kQueryThreads), 0, stream,
+                           ih, H, W, B, rects, n, hists, bad_count);
     return hipGetLastError();
 }
 

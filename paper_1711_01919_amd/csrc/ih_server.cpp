@@ -373,7 +373,7 @@ ih_status dispatch(ih_server* s, Batch& bt)
         const int32_t* d_rects = reinterpret_cast<const int32_t*>(work + ih::align_up((size_t)r.H * r.W, kAlign));
         uint32_t* d_hists = reinterpret_cast<uint32_t*>(const_cast<char*>(work) + ih::align_up((size_t)r.H * r.W, kAlign) +
                                                         ih::align_up(r.nq * sizeof(ih_rect), kAlign));
-        e = ih::launch_query(f.out, r.H, r.W, r.B, d_rects, (int64_t)r.nq, d_hists, nullptr, st);
+        e = ih::launch_query(f.out, r.H, r.W, r.B, d_rects, (int64_t)r.nq, d_hists, nullptr, false, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(r.hists_h, d_hists, r.nq * r.B * 4, hipMemcpyDeviceToHost, st);
     }

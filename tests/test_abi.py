@@ -64,8 +64,9 @@ class View(ctypes.Structure):
                 ("B", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
-def test_query_rejects_bad_rectangles_before_launch(lib):
-    f = lib.ih_query
+@pytest.mark.parametrize("name", ["ih_query", "ih_query_binmajor"])
+def test_query_rejects_bad_rectangles_before_launch(lib, name):
+    f = getattr(lib, name)
     f.argtypes = [ctypes.POINTER(View), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     v = View(0x1000, 10, 20, 4, None)
     for bad in ([0, 0, 20, 0], [-1, 0, 0, 0], [3, 0, 2, 0], [0, 5, 0, 4], [0, 0, 0, 10]):
