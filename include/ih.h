@@ -312,6 +312,17 @@ ih_status ih_submit(ih_server* server, int32_t stream_id, const uint8_t* frame_h
                     int32_t B, const ih_rect* rects_host, size_t nq, uint64_t* ticket);
 
 /*
+ * ih_submit_lut -- as ih_submit, with each pixel value v counted in bin
+ * lut_host[v] instead of Q(v) (the bin test of Eq. 1 as a table; HOST, 256
+ * entries, non-decreasing, each below B, copied before the call returns).
+ * Requests with and without tables share batches.  Errors: those of
+ * ih_submit, and IH_ERR_INVALID_ARG for a null or invalid table.
+ */
+ih_status ih_submit_lut(ih_server* server, int32_t stream_id, const uint8_t* frame_host, int32_t H, int32_t W,
+                        int32_t B, const uint8_t* lut_host, const ih_rect* rects_host, size_t nq,
+                        uint64_t* ticket);
+
+/*
  * ih_poll -- IH_NOT_READY until the request has finished; then copies its
  * nq*B histograms to hists_host (HOST, may be NULL), fills *t (may be NULL),
  * forgets the ticket and returns the request's status.  Unknown or already

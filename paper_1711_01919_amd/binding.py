@@ -114,12 +114,13 @@ def _load() -> ctypes.CDLL:
         f.restype = ctypes.c_int
     lib.ih_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.ih_submit.argtypes = [vp, i32, vp, i32, i32, i32, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
+    lib.ih_submit_lut.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
     lib.ih_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(Timing)]
     lib.ih_server_query_latest.argtypes = [vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.ih_server_stats.argtypes = [vp, ctypes.POINTER(ServerCounters)]
     lib.ih_server_destroy.argtypes = [vp]
     lib.ih_server_hold.argtypes = [vp, i32]
-    for f in (lib.ih_server_create, lib.ih_submit, lib.ih_poll, lib.ih_server_query_latest,
+    for f in (lib.ih_server_create, lib.ih_submit, lib.ih_submit_lut, lib.ih_poll, lib.ih_server_query_latest,
               lib.ih_server_stats, lib.ih_server_destroy, lib.ih_server_hold):
         f.restype = ctypes.c_int
     lib.ih_transfer_pipeline.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), sz, i32, i32, i32, i32,
@@ -347,15 +348,24 @@ class Server:
         self._h = h
         self._shape = {}
 
-    def submit(self, stream_id: int, frame: np.ndarray, B: int, rects=None) -> int:
+    def submit(self, stream_id: int, frame: np.ndarray, B: int, rects=None, lut=None) -> int:
+        """ih_submit, or ih_submit_lut when a 256-entry bin table is given."""
         frame = np.ascontiguousarray(frame, dtype=np.uint8)
         if frame.ndim != 2:
             raise ValueError("frame must be 2-D")
         H, W = frame.shape
         r = np.ascontiguousarray(rects if rects is not None else np.zeros((0, 4)), dtype=np.int32).reshape(-1, 4)
         t = ctypes.c_uint64()
-        _check(lib.ih_submit(self._h, stream_id, frame.ctypes.data, H, W, B,
-                             r.ctypes.data if len(r) else None, len(r), ctypes.byref(t)), "ih_submit")
+        rp = r.ctypes.data if len(r) else None
+        if lut is None:
+            _check(lib.ih_submit(self._h, stream_id, frame.ctypes.data, H, W, B, rp, len(r), ctypes.byref(t)),
+                   "ih_submit")
+        else:
+            table = np.ascontiguousarray(lut, dtype=np.uint8)
+            if table.shape != (256,):
+                raise ValueError("lut must hold 256 entries")
+            _check(lib.ih_submit_lut(self._h, stream_id, frame.ctypes.data, H, W, B, table.ctypes.data, rp,
+                                     len(r), ctypes.byref(t)), "ih_submit_lut")
         self._shape[t.value] = (len(r), B)
         return t.value
 

@@ -193,6 +193,8 @@ struct Request {
     // device blocks (arena offsets): the integral histogram, and the rest
     size_t ih_off = 0, ih_bytes = 0, work_off = 0, work_bytes = 0;
     ih::Geom geom{};
+    bool has_lut = false;    // bins from `lut` (copied at submit) instead of Q(v)
+    uint8_t lut[256] = {};
     ih_timing t{0, 0, 0};
     ih_status status = IH_OK;
     std::string detail;      // error text recorded on the scheduler thread
@@ -244,11 +246,13 @@ namespace {
 
 size_t ih_bytes_of(int32_t H, int32_t W, int32_t B) { return (size_t)H * W * B * 4; }
 
-// Device bytes of everything except the integral histogram.
-size_t work_bytes_of(const ih::Geom& g, size_t nq)
+// Device bytes of everything except the integral histogram: frame,
+// rectangles, results, carries and, for table bins, the table.
+size_t work_bytes_of(const ih::Geom& g, size_t nq, bool lut)
 {
     return ih::align_up((size_t)g.H * g.W, kAlign) + ih::align_up(nq * sizeof(ih_rect), kAlign) +
-           ih::align_up(nq * g.B * 4, kAlign) + ih::frame_scratch_words(g) * 4 + kAlign;
+           ih::align_up(nq * g.B * 4, kAlign) + ih::align_up(ih::frame_scratch_words(g) * 4, kAlign) +
+           (lut ? 256 : 0) + kAlign;
 }
 
 void release_pinned(ih_server* s, Request& r)
@@ -348,11 +352,15 @@ ih_status dispatch(ih_server* s, Batch& bt)
         uint32_t* d_scratch = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_hists) +
                                                           ih::align_up(r.nq * r.B * 4, kAlign));
         uint32_t* d_out = reinterpret_cast<uint32_t*>(s->d_arena + r.ih_off);
+        uint32_t* d_lut = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_scratch) +
+                                                      ih::align_up(ih::frame_scratch_words(r.geom) * 4, kAlign));
         hipError_t e = hipMemcpyAsync(d_frame, r.frame_h, (size_t)r.H * r.W, hipMemcpyHostToDevice, st);
         if (e == hipSuccess && r.nq)
             e = hipMemcpyAsync(d_rects, r.rects_h, r.nq * sizeof(ih_rect), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && r.has_lut) e = ih::launch_lut_store(r.lut, d_lut, st);
         if (e != hipSuccess) return hip_fail(e, "request upload");
-        frames.push_back(ih::frame_args(d_frame, d_out, d_scratch, r.geom));
+        frames.push_back(ih::frame_args(d_frame, d_out, d_scratch, r.geom,
+                                        r.has_lut ? reinterpret_cast<const uint8_t*>(d_lut) : nullptr));
         nt.push_back(0);
     }
     ih::BatchImage img;
@@ -515,31 +523,11 @@ void scheduler(ih_server* s)
     }
 }
 
-}  // namespace
-
-extern "C" {
-
-ih_status ih_server_create(const ih_server_config* cfg, ih_server** out)
-{
-    if (!cfg || !out) return fail(IH_ERR_INVALID_ARG, "cfg and out must be non-null");
-    *out = nullptr;
-    if (cfg->hbm_budget_bytes < (1u << 20)) return fail(IH_ERR_INVALID_ARG, "budget must be at least 1 MiB");
-    if (cfg->max_slots < 1 || cfg->n_hip_streams < 1 || cfg->n_hip_streams > 16 || cfg->max_batch < 1)
-        return fail(IH_ERR_INVALID_ARG, "max_slots, max_batch >= 1 and n_hip_streams in [1, 16] required");
-    ih_server* s = new ih_server;
-    s->cfg = *cfg;
-    s->pinned.set_arena_bytes(cfg->pinned_bytes ? cfg->pinned_bytes : (1ull << 30));
-    if (hipGetDevice(&s->device) != hipSuccess) {
-        (void)hipGetLastError();
-        s->device = 0;
-    }
-    s->worker = std::thread(scheduler, s);
-    *out = s;
-    return IH_OK;
-}
-
-ih_status ih_submit(ih_server* s, int32_t stream_id, const uint8_t* frame_host, int32_t H, int32_t W,
-                    int32_t B, const ih_rect* rects_host, size_t nq, uint64_t* ticket)
+// Validate and queue one request (ih_submit, ih_submit_lut).  The frame,
+// rectangles and bin table are copied before it returns.
+ih_status submit_request(ih_server* s, int32_t stream_id, const uint8_t* frame_host, int32_t H, int32_t W,
+                         int32_t B, const uint8_t* lut_host, const ih_rect* rects_host, size_t nq,
+                         uint64_t* ticket)
 {
     const uint64_t t0 = now_ns();
     if (!s || !frame_host || !ticket || (nq && !rects_host))
@@ -550,12 +538,20 @@ ih_status ih_submit(ih_server* s, int32_t stream_id, const uint8_t* frame_host, 
         if (q.x0 < 0 || q.x0 > q.x1 || q.x1 >= W || q.y0 < 0 || q.y0 > q.y1 || q.y1 >= H)
             return fail(IH_ERR_INVALID_ARG, "rectangle %zu is outside the %dx%d frame", r, W, H);
     }
+    for (int v = 0; lut_host && v < 256; ++v) {
+        if ((int32_t)lut_host[v] >= B)
+            return fail(IH_ERR_INVALID_ARG, "lut[%d]=%d is not a bin below B=%d", v, lut_host[v], B);
+        if (v > 0 && lut_host[v] < lut_host[v - 1])
+            return fail(IH_ERR_INVALID_ARG, "lut decreases at %d (%d after %d)", v, lut_host[v], lut_host[v - 1]);
+    }
     auto r = std::make_shared<Request>();
     r->stream_id = stream_id;
     r->H = H; r->W = W; r->B = B; r->nq = nq;
     r->geom = ih::make_geom(H, W, B, ih::default_tile(H, W, B));
     r->ih_bytes = ih_bytes_of(H, W, B);
-    r->work_bytes = work_bytes_of(r->geom, nq);
+    r->has_lut = lut_host != nullptr;
+    if (r->has_lut) std::memcpy(r->lut, lut_host, 256);
+    r->work_bytes = work_bytes_of(r->geom, nq, r->has_lut);
     const size_t need = ih::align_up(r->ih_bytes, kAlign) + ih::align_up(r->work_bytes, kAlign) + (64u << 10);
     if (need > s->cfg.hbm_budget_bytes)
         return fail(IH_ERR_BUDGET, "request needs %zu device bytes, budget is %llu", need,
@@ -583,6 +579,42 @@ ih_status ih_submit(ih_server* s, int32_t stream_id, const uint8_t* frame_host, 
     }
     s->cv.notify_one();
     return IH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ih_status ih_server_create(const ih_server_config* cfg, ih_server** out)
+{
+    if (!cfg || !out) return fail(IH_ERR_INVALID_ARG, "cfg and out must be non-null");
+    *out = nullptr;
+    if (cfg->hbm_budget_bytes < (1u << 20)) return fail(IH_ERR_INVALID_ARG, "budget must be at least 1 MiB");
+    if (cfg->max_slots < 1 || cfg->n_hip_streams < 1 || cfg->n_hip_streams > 16 || cfg->max_batch < 1)
+        return fail(IH_ERR_INVALID_ARG, "max_slots, max_batch >= 1 and n_hip_streams in [1, 16] required");
+    ih_server* s = new ih_server;
+    s->cfg = *cfg;
+    s->pinned.set_arena_bytes(cfg->pinned_bytes ? cfg->pinned_bytes : (1ull << 30));
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        (void)hipGetLastError();
+        s->device = 0;
+    }
+    s->worker = std::thread(scheduler, s);
+    *out = s;
+    return IH_OK;
+}
+
+ih_status ih_submit(ih_server* s, int32_t stream_id, const uint8_t* frame_host, int32_t H, int32_t W,
+                    int32_t B, const ih_rect* rects_host, size_t nq, uint64_t* ticket)
+{
+    return submit_request(s, stream_id, frame_host, H, W, B, nullptr, rects_host, nq, ticket);
+}
+
+ih_status ih_submit_lut(ih_server* s, int32_t stream_id, const uint8_t* frame_host, int32_t H, int32_t W,
+                        int32_t B, const uint8_t* lut_host, const ih_rect* rects_host, size_t nq, uint64_t* ticket)
+{
+    if (!lut_host) return fail(IH_ERR_INVALID_ARG, "lut must be non-null");
+    return submit_request(s, stream_id, frame_host, H, W, B, lut_host, rects_host, nq, ticket);
 }
 
 ih_status ih_poll(ih_server* s, uint64_t ticket, uint32_t* hists_host, ih_timing* t)

@@ -68,6 +68,36 @@ def test_alone_equals_mix_equals_oracle(ihb, orc):
         assert np.array_equal(mix[k], oracle_hists(orc, I, B, rects)), k
 
 
+def test_bin_tables_in_mixed_batches(ihb, orc):
+    """Requests with bin tables (random edges) and with uniform bins share
+    batches; each equals the oracle's table-binned or uniform result, alone
+    and in the mix."""
+    from paper_1711_01919_amd import synth
+    rng = np.random.default_rng(33)
+    reqs = []
+    for k in range(24):
+        H, W = [(240, 320), (101, 203), (480, 640)][k % 3]
+        B = [16, 32, 64, 100][int(rng.integers(0, 4))]
+        I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+        rects = synth.random_rects(rng, H, W, int(rng.integers(1, 50)))
+        lut = None
+        if k % 2 == 0:
+            edges = np.sort(rng.integers(0, 257, size=B - 1))
+            lut = np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8)
+        reqs.append((k % 4, I, B, rects, lut))
+    results = {}
+    for cfg in (dict(max_slots=1, n_hip_streams=1, max_batch=1), dict(max_slots=16, n_hip_streams=3, max_batch=6)):
+        srv = ihb.Server(budget_bytes=2 << 30, **cfg)
+        tickets = [srv.submit(sid, I, B, rects, lut=lut) for sid, I, B, rects, lut in reqs]
+        results[cfg["max_batch"]] = [srv.wait(t)[0] for t in tickets]
+        srv.close()
+    for k, (sid, I, B, rects, lut) in enumerate(reqs):
+        ref = orc.integral_histogram(I, B) if lut is None else orc.integral_histogram_lut(I, B, lut)
+        want = orc.region_histogram(ref, rects)
+        assert np.array_equal(results[1][k], want), k
+        assert np.array_equal(results[6][k], want), k
+
+
 def test_backpressure_under_small_budget(ihb, orc):
     """Budget for about two 720p B=64 requests at once: the rest wait, none fail."""
     rng = np.random.default_rng(32)
