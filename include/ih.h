@@ -162,6 +162,11 @@ typedef struct {
                                    non-decreasing, each < B), copied when the
                                    plan is created; such frames take tiles at
                                    most 64 wide and are not autotuned         */
+    int32_t binmajor;           /* 0: out in H x W x B; 1: out in the bin-major
+                                   b x h x w layout of ih_compute_binmajor
+                                   (uniform bins only: lut must be NULL; the
+                                   frame takes that call's tiles, whatever the
+                                   options force, and is not autotuned)       */
 } ih_frame_desc;
 
 typedef struct {

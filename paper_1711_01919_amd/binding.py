@@ -47,7 +47,7 @@ class PhaseTimes(ctypes.Structure):
 
 class FrameDesc(ctypes.Structure):
     _fields_ = [("frame", ctypes.c_void_p), ("out", ctypes.c_void_p), ("H", ctypes.c_int32),
-                ("W", ctypes.c_int32), ("B", ctypes.c_int32), ("lut", ctypes.c_void_p)]
+                ("W", ctypes.c_int32), ("B", ctypes.c_int32), ("lut", ctypes.c_void_p), ("binmajor", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):
@@ -277,16 +277,20 @@ class BatchPlan:
     keeps references to them."""
 
     def __init__(self, frames, outs, bins, autotune=False, use_graph=True, tile=None,
-                 nontemporal=-1, stream=None, group_bytes=0, luts=None):
+                 nontemporal=-1, stream=None, group_bytes=0, luts=None, binmajor=None):
         """group_bytes > 0 pipelines the plan in groups of about that many
         output bytes (see ih_batch_options in include/ih.h).  luts: None, or
-        per frame None (uniform bins) or a 256-entry bin table."""
+        per frame None (uniform bins) or a 256-entry bin table.  binmajor:
+        None, or per frame whether its output takes the (B, H, W) layout."""
         if not (len(frames) == len(outs) == len(bins)) or len(frames) == 0:
             raise ValueError("frames, outs and bins must be equally long and non-empty")
         tables = [None] * len(frames) if luts is None else [
             None if t is None else np.ascontiguousarray(t, dtype=np.uint8) for t in luts]
         if len(tables) != len(frames) or any(t is not None and t.shape != (256,) for t in tables):
             raise ValueError("luts must give one 256-entry table (or None) per frame")
+        layouts = [False] * len(frames) if binmajor is None else [bool(x) for x in binmajor]
+        if len(layouts) != len(frames):
+            raise ValueError("binmajor must give one flag per frame")
         descs = (FrameDesc * len(frames))()
         for k, (f, o, b) in enumerate(zip(frames, outs, bins)):
             if f.dtype != torch.uint8 or f.dim() != 2 or not f.is_cuda or not f.is_contiguous():
@@ -295,7 +299,7 @@ class BatchPlan:
             if o.dtype != torch.uint32 or not o.is_cuda or not o.is_contiguous() or o.numel() < H * W * b:
                 raise ValueError(f"out {k} must be a contiguous uint32 CUDA tensor with H*W*B elements")
             descs[k] = FrameDesc(_ptr(f), _ptr(o), H, W, int(b),
-                                 None if tables[k] is None else tables[k].ctypes.data)
+                                 None if tables[k] is None else tables[k].ctypes.data, 1 if layouts[k] else 0)
         tx, ty = tile if tile else (0, 0)
         opt = BatchOptions(1 if autotune else 0, 1 if use_graph else 0, tx, ty, int(nontemporal),
                            int(group_bytes))

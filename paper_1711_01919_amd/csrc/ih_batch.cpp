@@ -148,9 +148,10 @@ ih_status build_plan(ih_batch_plan* p)
         if (e != hipSuccess) return hip_fail(e, "upload bin tables");
     }
     std::vector<ih::FrameArgs> frames(n);
-    std::vector<char> nt(n);
+    std::vector<char> nt(n), bm(n);
     int64_t total_out = 0;
     for (size_t k = 0; k < n; ++k) {
+        bm[k] = p->descs[k].binmajor ? 1 : 0;
         const int32_t li = p->lut_index.empty() ? -1 : p->lut_index[k];
         const uint8_t* dl = li < 0 ? nullptr : static_cast<const uint8_t*>(p->d_luts) + (size_t)li * 256;
         frames[k] = ih::frame_args(p->descs[k].frame, p->descs[k].out,
@@ -160,7 +161,7 @@ ih_status build_plan(ih_batch_plan* p)
     }
     const int64_t ng = std::min<int64_t>(group_count(total_out, p->group_bytes), (int64_t)n);
     if (ng <= 1) {
-        ih::build_batch_image(frames, nt, &p->image);
+        ih::build_batch_image(frames, nt, &p->image, false, &bm);
         e = hipMalloc(&p->d_image, p->image.bytes());
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -183,8 +184,8 @@ ih_status build_plan(ih_batch_plan* p)
         } while (k1 < n && (acc < goal || g == ng - 1) && (int64_t)(n - k1) > ng - 1 - g);
         PlanGroup G;
         std::vector<ih::FrameArgs> sub(frames.begin() + k0, frames.begin() + k1);
-        std::vector<char> subnt(nt.begin() + k0, nt.begin() + k1);
-        ih::build_batch_image(sub, subnt, &G.image, true);
+        std::vector<char> subnt(nt.begin() + k0, nt.begin() + k1), subbm(bm.begin() + k0, bm.begin() + k1);
+        ih::build_batch_image(sub, subnt, &G.image, true, &subbm);
         G.dev_off = bytes;
         bytes = ih::align_up(bytes + G.image.bytes(), 256);
         p->groups.push_back(std::move(G));
@@ -378,7 +379,7 @@ ih_status autotune(ih_batch_plan* p, hipStream_t s)
 {
     std::map<TuneKey, std::vector<size_t>> classes;
     for (size_t k = 0; k < p->descs.size(); ++k)
-        if (p->descs[k].lut == nullptr)                       // frames with bin tables keep their heuristic tile
+        if (p->descs[k].lut == nullptr && !p->descs[k].binmajor)   // table and bin-major frames keep their tile
             classes[TuneKey{p->descs[k].H, p->descs[k].W, p->descs[k].B, 0}].push_back(k);
     TuneCache& c = tune_cache();
     std::lock_guard<std::mutex> lock(c.mu);
@@ -428,8 +429,12 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
         if (!d.frame || !d.out) return fail(IH_ERR_INVALID_ARG, "frame %zu: null pointer", k);
         if (ih_status st = ih::check_shape(d.H, d.W, d.B)) return st;
         if (reinterpret_cast<uintptr_t>(d.out) & 3u) return fail(IH_ERR_INVALID_ARG, "frame %zu: out misaligned", k);
-        if (forced && !ih::tile_supported(d.B, ih::TileChoice{o.tile_x, o.tile_y, false}))
+        if (forced && !d.binmajor && !ih::tile_supported(d.B, ih::TileChoice{o.tile_x, o.tile_y, false}))
             return fail(IH_ERR_INVALID_ARG, "tile %dx%d not supported for B=%d", o.tile_x, o.tile_y, d.B);
+        if (d.binmajor != 0 && d.binmajor != 1)
+            return fail(IH_ERR_INVALID_ARG, "frame %zu: binmajor must be 0 or 1", k);
+        if (d.binmajor && d.lut)
+            return fail(IH_ERR_INVALID_ARG, "frame %zu: bin-major frames take uniform bins (lut must be NULL)", k);
         if (d.lut) {
             if (forced && o.tile_x > 64)
                 return fail(IH_ERR_INVALID_ARG, "frame %zu: bin tables take tiles at most 64 wide", k);
@@ -489,6 +494,10 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
         p->tiles[k].nontemporal = false;
         p->descs[k].lut = nullptr;
     }
+    // Bin-major frames: the tiles of ih_compute_binmajor (64-column tiles
+    // the bin-major pass is written for).
+    for (size_t k = 0; st == IH_OK && k < n; ++k)
+        if (p->descs[k].binmajor) p->tiles[k] = ih::binmajor_tile(frames[k].H, frames[k].W, frames[k].B);
     if (st == IH_OK) st = build_plan(p);
     if (st == IH_OK && p->use_graph) {
         st = capture(p, -1, &p->exec_all);
@@ -551,7 +560,8 @@ ih_status ih_batch_plan_info(const ih_batch_plan* p, ih_batch_info* info)
     int32_t launches = 0, tile_launches = 0;
     auto count = [&](const ih::BatchImage& img) {
         launches += (int32_t)img.launches.size();
-        for (const ih::BatchLaunch& l : img.launches) tile_launches += l.kind == ih::BatchLaunch::kTile;
+        for (const ih::BatchLaunch& l : img.launches)
+            tile_launches += l.kind == ih::BatchLaunch::kTile || l.kind == ih::BatchLaunch::kTileBM;
     };
     if (p->groups.empty()) count(p->image);
     for (const PlanGroup& G : p->groups) count(G.image);

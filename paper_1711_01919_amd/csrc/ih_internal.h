@@ -127,6 +127,13 @@ int64_t scan_b_blocks(const Geom& g);
 // Tile pass writing the bin-major layout (entry (x, y, b) at (b*H + y)*W + x)
 // from the carries of a frame whose geometry has 64-column tiles.
 hipError_t launch_tile_bm(const FrameArgs& f, hipStream_t stream);
+// Bins per bin-major work item (largest power of two up to 16 dividing B),
+// work items of a frame, and the batched pass over frames sharing one group
+// width bg (a job per frame, `begin` its first item).
+int bm_group(int B);
+int64_t tile_bm_items(const Geom& g);
+hipError_t launch_tile_bm_batch(int bg, const FrameArgs* frames, const Job* jobs, int32_t njobs, int64_t nitems,
+                                hipStream_t stream);
 
 // Copy a host bin table (256 bytes, passed by value as a kernel argument) to
 // device memory dst (64 uint32, 4-byte aligned), in stream order.

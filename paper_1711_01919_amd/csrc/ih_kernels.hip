@@ -864,16 +864,13 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, int lane)
     return v;
 }
 
+// Items of a frame: nTY * nTX * (B / BG), one wave each.
 template <int BG>
-__global__ __launch_bounds__(kWave * kWavesPerBlock)
-void tile_bm_kernel(FrameArgs f)
+__device__ __forceinline__ void tile_bm_body(const FrameArgs& f, int64_t item)
 {
     const Geom& g = f.g;
     const int B = g.B, H = g.H, W = g.W;
     const int n_groups = B / BG;
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
-    const int64_t nitems = (int64_t)g.nTY * g.nTX * n_groups;
-    if (item >= nitems) return;                           // whole wave leaves together
     const int lane = threadIdx.x % kWave;
     const int grp = (int)(item % n_groups);
     const int64_t tile = item / n_groups;
@@ -939,6 +936,29 @@ void tile_bm_kernel(FrameArgs f)
             }
         }
     }
+}
+
+template <int BG>
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+void tile_bm_kernel(FrameArgs f)
+{
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+    if (item >= (int64_t)f.g.nTY * f.g.nTX * (f.g.B / BG)) return;     // whole wave leaves together
+    tile_bm_body<BG>(f, item);
+}
+
+// Many bin-major frames with the same bin group BG: one wave per item over
+// the job table (a job per frame, `begin` its first item).
+template <int BG>
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+void tile_bm_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs,
+                          int64_t nitems)
+{
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+    if (item >= nitems) return;                                        // whole wave leaves together
+    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, item));
+    const FrameArgs f = cload(frames, jb.frame);
+    tile_bm_body<BG>(f, item - jb.begin);
 }
 
 // A bin table passed by value as a kernel argument, written to device memory.
@@ -1148,7 +1168,7 @@ int32_t tile_resident_blocks(const TileVariant& v)
 // Largest power of two up to 16 that divides B: the bins of one bin-major
 // work item (more bins per item keep more ballot masks and carries live than
 // the scalar registers hold).
-static int bm_group(int B)
+int bm_group(int B)
 {
     int bg = 16;
     while (B % bg != 0) bg >>= 1;
@@ -1168,6 +1188,24 @@ hipError_t launch_tile_bm(const FrameArgs& f, hipStream_t stream)
     case 4: hipLaunchKernelGGL(tile_bm_kernel<4>, grid, block, 0, stream, f); break;
     case 2: hipLaunchKernelGGL(tile_bm_kernel<2>, grid, block, 0, stream, f); break;
     default: hipLaunchKernelGGL(tile_bm_kernel<1>, grid, block, 0, stream, f); break;
+    }
+    return hipGetLastError();
+}
+
+int64_t tile_bm_items(const Geom& g) { return (int64_t)g.nTY * g.nTX * (g.B / bm_group(g.B)); }
+
+hipError_t launch_tile_bm_batch(int bg, const FrameArgs* frames, const Job* jobs, int32_t njobs, int64_t nitems,
+                                hipStream_t stream)
+{
+    if (nitems <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((nitems + kWavesPerBlock - 1) / kWavesPerBlock);
+    const dim3 grid(blocks), block(kWave * kWavesPerBlock);
+    switch (bg) {
+    case 16: hipLaunchKernelGGL(tile_bm_batch_kernel<16>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    case 8: hipLaunchKernelGGL(tile_bm_batch_kernel<8>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    case 4: hipLaunchKernelGGL(tile_bm_batch_kernel<4>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    case 2: hipLaunchKernelGGL(tile_bm_batch_kernel<2>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    default: hipLaunchKernelGGL(tile_bm_batch_kernel<1>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
     }
     return hipGetLastError();
 }

@@ -53,7 +53,7 @@ static int32_t cu_count_cached()
 }
 
 void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<char>& nontemporal,
-                       BatchImage* img, bool leave_room)
+                       BatchImage* img, bool leave_room, const std::vector<char>* binmajor)
 {
     const size_t n = frames.size();
     std::vector<std::vector<Job>> tables;
@@ -110,6 +110,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
     std::map<TileVariant, std::vector<Job>> byv;
     std::map<TileVariant, int64_t> items;
     for (size_t k = 0; k < n; ++k) {
+        if (binmajor && (*binmajor)[k]) continue;
         const Geom& g = frames[k].g;
         const int32_t n_int = interior_groups(g, frames[k].frame, frames[k].out);
         const int32_t parts[2][2] = {{0, n_int}, {n_int, g.nJG - n_int}};
@@ -138,6 +139,25 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         launches.push_back(l);
         tables.push_back(std::move(kv.second));
     }
+    // Bin-major frames: one launch per bin-group width, one wave per item.
+    for (int bg : {16, 8, 4, 2, 1}) {
+        if (!binmajor) break;
+        std::vector<Job> jobs;
+        int64_t begin = 0;
+        for (size_t k = 0; k < n; ++k) {
+            if (!(*binmajor)[k] || bm_group(frames[k].g.B) != bg) continue;
+            jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
+            begin += tile_bm_items(frames[k].g);
+        }
+        if (jobs.empty()) continue;
+        BatchLaunch l;
+        l.kind = BatchLaunch::kTileBM;
+        l.bg = bg;
+        l.n = begin;
+        l.njobs = (int32_t)jobs.size();
+        launches.push_back(l);
+        tables.push_back(std::move(jobs));
+    }
 
     size_t bytes = align_up(n * sizeof(FrameArgs), 256);
     for (size_t t = 0; t < tables.size(); ++t) {
@@ -164,6 +184,7 @@ hipError_t enqueue_batch(const BatchImage& img, const void* dev_image, int phase
         case BatchLaunch::kScanA: e = launch_scan_a_batch(l.parts, fr, jobs, l.njobs, l.n, s); break;
         case BatchLaunch::kScanB: e = launch_scan_b_batch(l.parts, fr, jobs, l.njobs, l.n, s); break;
         case BatchLaunch::kTile: e = launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid, s); break;
+        case BatchLaunch::kTileBM: e = launch_tile_bm_batch(l.bg, fr, jobs, l.njobs, l.n, s); break;
         }
         if (e != hipSuccess) return e;
     }

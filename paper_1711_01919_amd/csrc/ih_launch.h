@@ -11,13 +11,14 @@
 namespace ih {
 
 struct BatchLaunch {
-    enum Kind { kCount, kScanA, kScanB, kTile } kind = kCount;
+    enum Kind { kCount, kScanA, kScanB, kTile, kTileBM } kind = kCount;
     int tx = 64;               // kCount: tile width of the frames it covers
     int parts = 1;             // kScanA, kScanB: scan form (scan_parts of its frames)
+    int bg = 0;                // kTileBM: bins per work item of its frames
     TileVariant v{};           // kTile: compiled kernel variant
     size_t jobs_off = 0;       // byte offset of this launch's job table in the image
     int32_t njobs = 0;
-    int64_t n = 0;             // blocks (kCount, kScan*) or work items (kTile)
+    int64_t n = 0;             // blocks (kCount, kScan*) or work items (kTile, kTileBM)
     int32_t grid = 0;          // kTile: persistent workgroups
     size_t lds = 0;            // kCount: dynamic LDS bytes
 };
@@ -37,8 +38,10 @@ size_t frame_scratch_words(const Geom& g);
 // nontemporal[k] picks the store flavour of frame k.  With leave_room, the
 // persistent tile grid keeps one workgroup slot per compute unit free (when
 // the kernel fits two or more per unit) for kernels running beside it.
+// binmajor (may be null): frames whose output takes the bin-major layout
+// (their geometry has 64-column tiles; their tile pass is tile_bm).
 void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<char>& nontemporal,
-                       BatchImage* img, bool leave_room = false);
+                       BatchImage* img, bool leave_room = false, const std::vector<char>* binmajor = nullptr);
 
 // Enqueue the image's launches of one phase (-1: all phases) on s.  dev_image
 // is a device copy of img.host that stays valid until the work has run.

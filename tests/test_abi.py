@@ -112,10 +112,11 @@ def test_compute_lut_rejects_bad_tables_before_launch(lib):
     assert f(fake, 4, 4, 4, good, fake + 2, None) == 1
 
 
-def test_batch_plan_rejects_bad_tables_before_launch(lib):
+def test_batch_plan_rejects_bad_tables_and_layouts_before_launch(lib):
     class FrameDesc(ctypes.Structure):
         _fields_ = [("frame", ctypes.c_void_p), ("out", ctypes.c_void_p), ("H", ctypes.c_int32),
-                    ("W", ctypes.c_int32), ("B", ctypes.c_int32), ("lut", ctypes.c_void_p)]
+                    ("W", ctypes.c_int32), ("B", ctypes.c_int32), ("lut", ctypes.c_void_p),
+                    ("binmajor", ctypes.c_int32)]
     f = lib.ih_batch_plan_create
     f.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.POINTER(ctypes.c_void_p)]
@@ -124,6 +125,11 @@ def test_batch_plan_rejects_bad_tables_before_launch(lib):
     too_big = (ctypes.c_uint8 * 256)(*([0] * 255 + [8]))
     plan = ctypes.c_void_p()
     for table in (decreasing, too_big):
-        d = (FrameDesc * 1)(FrameDesc(fake, fake, 4, 4, 8, ctypes.cast(table, ctypes.c_void_p)))
+        d = (FrameDesc * 1)(FrameDesc(fake, fake, 4, 4, 8, ctypes.cast(table, ctypes.c_void_p), 0))
         assert f(d, 1, None, None, ctypes.byref(plan)) == 1
+        assert not plan.value
+    good = (ctypes.c_uint8 * 256)(*([0] * 256))
+    for d in (FrameDesc(fake, fake, 4, 4, 8, None, 2),                                 # no such layout
+              FrameDesc(fake, fake, 4, 4, 8, ctypes.cast(good, ctypes.c_void_p), 1)):  # bin-major with a table
+        assert f((FrameDesc * 1)(d), 1, None, None, ctypes.byref(plan)) == 1
         assert not plan.value

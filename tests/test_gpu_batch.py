@@ -274,3 +274,43 @@ def test_plan_with_bin_tables(ihb, orc, group_bytes, use_graph, autotune):
         for k in range(len(frames)):
             assert np.array_equal(outs[k].cpu().numpy(), refs[k]), (rep, k)
     plan.close()
+
+
+@pytest.mark.parametrize("group_bytes,use_graph", [(0, True), (0, False), (1, True)])
+def test_plan_with_binmajor_frames(ihb, orc, group_bytes, use_graph):
+    """Bin-major outputs (the paper's b x h x w) beside H x W x B ones, uniform
+    and table-binned, in one plan: one launch per bin-group width for the
+    bin-major pass; graph replays, direct launches and one frame per pipeline
+    group all give the oracle's bits."""
+    rng = np.random.default_rng(26)
+    shapes = [(240, 320, 64, 1), (97, 203, 48, 1), (130, 67, 5, 1), (300, 257, 64, 0), (61, 64, 128, 1),
+              (200, 130, 32, 0), (33, 384, 256, 1)]
+    frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _, _ in shapes]
+    bins = [b for _, _, b, _ in shapes]
+    layouts = [bool(m) for _, _, _, m in shapes]
+    luts = [None] * len(shapes)
+    edges = np.sort(rng.integers(0, 257, size=31))
+    luts[5] = np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8)
+    fr = [torch.from_numpy(f).cuda() for f in frames]
+    outs = [torch.full(((b, h, w) if m else (h, w, b)), 0xA5A5A5A5, dtype=torch.uint32, device="cuda")
+            for h, w, b, m in shapes]
+    refs = []
+    for f, b, m, t in zip(frames, bins, layouts, luts):
+        if m:
+            refs.append(orc.integral_histogram_binmajor(f, b))
+        else:
+            refs.append(orc.integral_histogram(f, b) if t is None else orc.integral_histogram_lut(f, b, t))
+    plan = ihb.BatchPlan(fr, outs, bins, use_graph=use_graph, group_bytes=group_bytes, luts=luts,
+                         binmajor=layouts)
+    for k, m in enumerate(layouts):
+        if m:
+            assert plan.frame_tile(k)[0] == 64
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for k in range(len(frames)):
+            assert np.array_equal(outs[k].cpu().numpy(), refs[k]), (rep, k, shapes[k])
+    plan.close()
