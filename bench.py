@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # reads on the same counters).  Valid only for the kernel source and tile they
 # were taken with; any other combination reports null.
 TRAFFIC_RECORD = {
-    "kernel_src_sha256": "760567872d30850491d30acbda6c0683c6c7975e0b800301c969ff3077bfbf2d",
+    "kernel_src_sha256": "0567a68bef331516cbc9325f68daee3086db17d778e58e6beb9ddc933c8625e9",
     "workload": "disc_sequence_64x1080x1920_B64", "tile": [128, 216], "nontemporal": False,
-    "fetch_bytes": 336931.0 * 2.0 * 1024, "write_bytes": 33177600.0 * 1.0 * 1024,
+    "fetch_bytes": 336929.0 * 2.0 * 1024, "write_bytes": 33177600.0 * 1.0 * 1024,
 }
 
 
@@ -499,6 +499,21 @@ def main():
     pplan.close()
     log(f"[bench] pipelined plan: {pipelined}")
 
+    # the same frames with bin-major outputs (the paper's b x h x w layout),
+    # one plan over the same buffers viewed as (B, H, W)
+    bplan = ihb.BatchPlan([d_frames[k] for k in range(n)], [o.view(B, H, W) for o in outs], [B] * n,
+                          stream=stream, binmajor=[True] * n)
+    bplan.launch(stream)
+    torch.cuda.synchronize()
+    got = outs[n - 1].view(B, H, W)[:, H - 1].cpu().numpy().T
+    assert np.array_equal(got, orc.row_by_definition(frames[n - 1], B, H - 1)), "bin-major spot check failed"
+    ms_bm = timed(torch, stream, lambda: bplan.launch(stream), args.steps) / args.steps
+    binmajor = {"ms_per_step": ms_bm, "value": entries_step / (ms_bm / 1e3),
+                "hbm_frac": n * alg_bytes_frame / (ms_bm / 1e3) / 1e9 / HBM_PEAK_GBS,
+                "tile": list(bplan.frame_tile(0)[:2])}
+    bplan.close()
+    log(f"[bench] bin-major plan: {binmajor}")
+
 
     plan.close()
     del outs, plan
@@ -532,6 +547,7 @@ def main():
                        "speedup_batched": ms_plain / ms_step},
         "profiled_ms_per_step": ms_prof / args.steps,
         "pipelined_4GiB": pipelined,
+        "binmajor_batched": binmajor,
         "phase_ms_per_step": {k: ph[k] / args.steps for k in ("agg_ms", "scan_ms", "tile_ms")},
         "roofline": {"bound": "hbm", "kernel": "tile_batch_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
