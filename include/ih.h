@@ -164,9 +164,10 @@ typedef struct {
                                    most 64 wide and are not autotuned         */
     int32_t binmajor;           /* 0: out in H x W x B; 1: out in the bin-major
                                    b x h x w layout of ih_compute_binmajor
-                                   (uniform bins only: lut must be NULL; the
-                                   frame takes that call's tiles, whatever the
-                                   options force, and is not autotuned)       */
+                                   (uniform bins only: lut must be NULL; such
+                                   frames take 64-column tiles with bands
+                                   chosen over all of them, whatever the
+                                   options force, and are not autotuned)      */
 } ih_frame_desc;
 
 typedef struct {
