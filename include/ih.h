@@ -362,7 +362,7 @@ ih_status ih_server_destroy(ih_server* server);
  * event records per frame while on.
  */
 typedef struct {
-    double agg_ms;      /* per-tile bin counts                         */
+    double agg_ms;      /* count phase: row carries and per-tile counts */
     double scan_ms;     /* carry scans                                  */
     double tile_ms;     /* tile pass: binning, scans, output stores     */
     uint64_t frames;    /* frames recorded since ih_profile_enable      */

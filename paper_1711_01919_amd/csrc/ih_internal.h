@@ -91,6 +91,7 @@ struct TileVariant {
 TileVariant tile_variant(const Geom& g, bool nontemporal, bool guard, bool table = false);
 
 // ---- single frame: the three phases in order on one stream ----------------
+// kAgg: the count launch (row carries and per-tile column counts).
 enum class Phase { kAgg = 0, kScan = 1, kTile = 2 };
 constexpr int kNumPhases = 3;
 hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStream_t stream);
