@@ -135,6 +135,42 @@ def test_repeat_calls_identical(ihb, orc):
         assert np.array_equal(o.cpu().numpy(), ref)
 
 
+def test_scratch_reuse_and_tables_in_stream_order(ihb, orc):
+    """One stream, no synchronisation between calls: frames whose carries need
+    more and then less scratch (the stream's buffer is replaced once earlier
+    work has drained), and table-binned frames with different tables back to
+    back (each call's table is stored in stream order).  Every output equals
+    the oracle."""
+    rng = np.random.default_rng(15)
+    shapes = [(64, 96, 16), (700, 900, 64), (33, 47, 7), (480, 640, 32), (65, 129, 256), (300, 257, 100)]
+    frames, luts, refs = [], [], []
+    for k, (H, W, B) in enumerate(shapes):
+        I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+        lut = None
+        if k % 2:
+            edges = np.sort(rng.integers(0, 257, size=B - 1))
+            lut = np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8)
+        frames.append(I)
+        luts.append(lut)
+        refs.append(orc.integral_histogram(I, B) if lut is None else orc.integral_histogram_lut(I, B, lut))
+    dev = [torch.from_numpy(I).cuda() for I in frames]
+    outs = [torch.empty((H, W, B), dtype=torch.uint32, device="cuda") for H, W, B in shapes]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    for rep in range(2):
+        for o in outs:
+            o.fill_(0xA5A5A5A5)
+        torch.cuda.synchronize()
+        for f, o, (H, W, B), lut in zip(dev, outs, shapes, luts):
+            if lut is None:
+                ihb.compute(f, B, out=o, stream=s)
+            else:
+                ihb.compute_lut(f, B, lut, out=o, stream=s)
+        s.synchronize()
+        for k, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), refs[k]), (rep, k, shapes[k])
+
+
 def test_errors_leave_output_untouched(ihb):
     f = torch.zeros((8, 8), dtype=torch.uint8, device="cuda")
     out = torch.full((8 * 8 * 4,), 0xDEADBEEF, dtype=torch.uint32, device="cuda").view(8, 8, 4)
