@@ -29,11 +29,11 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64 = ctypes.c_int64
 
 
-def compile_oracle(out: Path = LIB, mutant: int = 0) -> Path:
-    """Compile the oracle with gcc.  ``mutant`` > 0 plants one deliberate
-    mistake (see the header of ih_oracle.c) for the pin tests."""
+def compile_oracle(out: Path = LIB, source: Path = SRC) -> Path:
+    """Compile the oracle with gcc.  ``source`` may name a patched copy of
+    ih_oracle.c (the pin tests compile copies with one mistake planted)."""
     out = Path(out)
-    cmd = ["gcc", *CFLAGS, f"-DIHREF_MUTANT={int(mutant)}", str(SRC), "-o", str(out) + ".tmp"]
+    cmd = ["gcc", *CFLAGS, str(source), "-o", str(out) + ".tmp"]
     subprocess.run(cmd, check=True, capture_output=True)
     os.replace(str(out) + ".tmp", out)
     return out
@@ -96,7 +96,7 @@ class Oracle:
         return out
 
     def integral_histogram_binmajor(self, I, B: int) -> np.ndarray:
-        """Algorithm 1 in the paper's order, stored bin-major: shape (B, H, W)."""
+        """Eq. 1 per bin plane, stored bin-major: shape (B, H, W)."""
         I, p = self._frame(I)
         H, W = I.shape
         out = np.empty((B, H, W), dtype=np.uint32)

@@ -16,8 +16,9 @@
  *                             (bins of arbitrary edges: the paper states Q as
  *                             membership of I(r,c) in bin b without fixing
  *                             the bins, Sec. 2.1)
- *   ihref_integral_histogram_binmajor  Algorithm 1 in the paper's own order:
- *                             bins outermost, stored b x h x w (Sec. 3.1)
+ *   ihref_integral_histogram_binmajor  Eq. 1 per bin plane as running sums
+ *                             along rows, then down columns, stored b x h x w
+ *                             (the paper's layout, Sec. 3.1)
  *   ihref_integral_rows       the same recursion continued over a block of
  *                             rows, for frames whose tensor does not fit RAM
  *   ihref_row_by_definition   one row of Eq. 1, summed directly (columns
@@ -38,29 +39,21 @@
  *     applied with r- = x0-1, c- = y0-1 (zero at -1), in modular uint32
  *     arithmetic.
  *
- * Planted mistakes: when compiled with -DIHREF_MUTANT=n (n >= 1) one deliberate
- * error is planted in the arithmetic, so that the test suite can show its pins
- * catch it.  The default build (IHREF_MUTANT undefined or 0) has none.
+ * The test suite shows that its pins catch plausible mistakes by compiling
+ * copies of this file with one mistake patched in; this file itself holds
+ * none and has no switch for them.
  */
 #include <stdint.h>
 #include <stddef.h>
 #include <string.h>
 #include <stdlib.h>
 
-#ifndef IHREF_MUTANT
-#define IHREF_MUTANT 0
-#endif
-
 /* Sec. 2.1: Q(I(r,c), b) is 1 when the value I(r,c) lies in bin b.  The paper
  * gives no bin edges; the bins here split [0,256) uniformly by
  * floor(v*B/256), so bin b holds the values v with 256*b <= v*B < 256*(b+1). */
 uint32_t ihref_Q(uint32_t v, uint32_t B)
 {
-#if IHREF_MUTANT == 1
-    return (v * B + 128u) >> 8;          /* planted: rounds instead of floors */
-#else
     return (v * B) >> 8;
-#endif
 }
 
 static uint32_t at(const uint32_t* Ht, int64_t W, int64_t B, int64_t x, int64_t y, int64_t b)
@@ -92,18 +85,8 @@ int ihref_integral_histogram(const uint8_t* I, int64_t H, int64_t W, int64_t B, 
             for (int64_t b = 0; b < B; ++b) {
                 uint32_t h = at(out, W, B, x - 1, y, b)
                            + at(out, W, B, x, y - 1, b)
-#if IHREF_MUTANT == 2
-                           ;                             /* planted: corner term dropped */
-#elif IHREF_MUTANT == 3
-                           + at(out, W, B, x - 1, y - 1, b);   /* planted: wrong sign */
-#else
                            - at(out, W, B, x - 1, y - 1, b);
-#endif
-#if IHREF_MUTANT == 4
-                if (q == (uint32_t)b && x > 0) h += 1u;     /* planted: first column loses its pixel */
-#else
                 if (q == (uint32_t)b) h += 1u;
-#endif
                 out[(y * W + x) * B + b] = h;
             }
         }
@@ -112,9 +95,11 @@ int ihref_integral_histogram(const uint8_t* I, int64_t H, int64_t W, int64_t B, 
 }
 
 /*
- * Sec. 2.2, Algorithm 1 with the loops in the listing's order -- bin, then
- * row, then column -- and the tensor stored bin-major, b x h x w, as the
- * paper lays it out (Sec. 3.1): entry (x, y, b) at (b*H + y)*W + x.
+ * Eq. 1 stored bin-major, b x h x w, as the paper lays the tensor out
+ * (Sec. 3.1, Fig. 2): entry (x, y, b) at (b*H + y)*W + x.  Each bin plane
+ * takes the double sum of Eq. 1 as two running sums: along every row first
+ * (the sum over columns c <= x of the bin indicator), then down every column
+ * of those row sums (the sum over rows r <= y).
  * Returns 0 on success, -1 on bad arguments.
  */
 int ihref_integral_histogram_binmajor(const uint8_t* I, int64_t H, int64_t W, int64_t B, uint32_t* out)
@@ -123,17 +108,15 @@ int ihref_integral_histogram_binmajor(const uint8_t* I, int64_t H, int64_t W, in
     for (int64_t b = 0; b < B; ++b) {
         uint32_t* P = out + b * H * W;
         for (int64_t y = 0; y < H; ++y) {
+            uint32_t run = 0;
             for (int64_t x = 0; x < W; ++x) {
-                const uint32_t left = x > 0 ? P[y * W + x - 1] : 0u;
-                const uint32_t up = y > 0 ? P[(y - 1) * W + x] : 0u;
-#if IHREF_MUTANT == 10
-                const uint32_t corner = (x > 0 && y > 0) ? P[(y - 1) * W + x] : 0u;   /* planted: wrong neighbour */
-#else
-                const uint32_t corner = (x > 0 && y > 0) ? P[(y - 1) * W + x - 1] : 0u;
-#endif
-                P[y * W + x] = left + up - corner + (ihref_Q(I[y * W + x], (uint32_t)B) == (uint32_t)b ? 1u : 0u);
+                run += ihref_Q(I[y * W + x], (uint32_t)B) == (uint32_t)b ? 1u : 0u;
+                P[y * W + x] = run;
             }
         }
+        for (int64_t y = 1; y < H; ++y)
+            for (int64_t x = 0; x < W; ++x)
+                P[y * W + x] += P[(y - 1) * W + x];
     }
     return 0;
 }
@@ -153,11 +136,7 @@ int ihref_integral_histogram_lut(const uint8_t* I, int64_t H, int64_t W, int64_t
         if ((int64_t)lut[v] >= B) return -1;
     for (int64_t y = 0; y < H; ++y) {
         for (int64_t x = 0; x < W; ++x) {
-#if IHREF_MUTANT == 9
-            const uint32_t q = lut[I[y * W + x] ^ 1u];         /* planted: neighbouring table entry */
-#else
             const uint32_t q = lut[I[y * W + x]];
-#endif
             for (int64_t b = 0; b < B; ++b) {
                 uint32_t h = at(out, W, B, x - 1, y, b) + at(out, W, B, x, y - 1, b)
                            - at(out, W, B, x - 1, y - 1, b);
@@ -193,11 +172,7 @@ int ihref_integral_rows(const uint8_t* I, int64_t H, int64_t W, int64_t B,
             for (int64_t b = 0; b < B; ++b) {
                 const uint32_t left = x > 0 ? cur[(x - 1) * B + b] : 0u;
                 const uint32_t above = up ? up[x * B + b] : 0u;
-#if IHREF_MUTANT == 6
-                const uint32_t corner = 0u;                  /* planted: corner term dropped */
-#else
                 const uint32_t corner = (up && x > 0) ? up[(x - 1) * B + b] : 0u;
-#endif
                 cur[x * B + b] = left + above - corner + (q == (uint32_t)b ? 1u : 0u);
             }
         }
@@ -217,11 +192,7 @@ int ihref_row_by_definition(const uint8_t* I, int64_t H, int64_t W, int64_t B,
     if (!I || !row_out || H <= 0 || W <= 0 || B < 1 || B > 256 || y < 0 || y >= H) return -1;
     uint32_t* colcount = (uint32_t*)calloc((size_t)(W * B), sizeof(uint32_t));
     if (!colcount) return -1;
-#if IHREF_MUTANT == 7
-    for (int64_t yy = 0; yy < y; ++yy)                    /* planted: row y itself left out */
-#else
     for (int64_t yy = 0; yy <= y; ++yy)
-#endif
         for (int64_t x = 0; x < W; ++x)
             colcount[x * B + ihref_Q(I[yy * W + x], (uint32_t)B)] += 1u;
     for (int64_t b = 0; b < B; ++b) {
@@ -261,13 +232,8 @@ int64_t ihref_region_histogram(const uint32_t* Ht, int64_t H, int64_t W, int64_t
         const int64_t x1 = rects[4 * i + 2], y1 = rects[4 * i + 3];
         if (x0 < 0 || y0 < 0 || x1 < x0 || y1 < y0 || x1 >= W || y1 >= H) return i + 1;
         for (int64_t b = 0; b < B; ++b) {
-#if IHREF_MUTANT == 5
-            const uint32_t h = at(Ht, W, B, x1, y1, b) - at(Ht, W, B, x0 - 1, y1, b)
-                             - at(Ht, W, B, x1, y0, b) + at(Ht, W, B, x0 - 1, y0, b); /* planted: off by one row */
-#else
             const uint32_t h = at(Ht, W, B, x1, y1, b) - at(Ht, W, B, x0 - 1, y1, b)
                              - at(Ht, W, B, x1, y0 - 1, b) + at(Ht, W, B, x0 - 1, y0 - 1, b);
-#endif
             hists[i * B + b] = h;
         }
     }
@@ -282,11 +248,7 @@ int ihref_rect_count(const uint8_t* I, int64_t H, int64_t W, int64_t B,
     if (x0 < 0 || y0 < 0 || x1 < x0 || y1 < y0 || x1 >= W || y1 >= H) return -1;
     memset(hist, 0, (size_t)B * sizeof(uint32_t));
     for (int64_t r = y0; r <= y1; ++r)
-#if IHREF_MUTANT == 8
-        for (int64_t c = x0; c < x1; ++c)                 /* planted: last column left out */
-#else
         for (int64_t c = x0; c <= x1; ++c)
-#endif
             hist[ihref_Q(I[r * W + c], (uint32_t)B)] += 1u;
     return 0;
 }

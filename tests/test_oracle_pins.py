@@ -12,7 +12,8 @@ fix, none of which re-types the oracle's own recursion.
   - table binning: brute force with the table's one-hot, the uniform table
     equals Q, empty bins stay zero;
   - bin-major storage: brute force per bin plane;
-  - planted mistakes: every mutant build of the oracle must fail a pin.
+  - planted mistakes: every copy of the oracle with one plausible mistake
+    patched in must fail a pin.
 """
 import json
 from pathlib import Path
@@ -260,11 +261,66 @@ def test_rejects_bad_arguments(orc):
             orc.region_histogram(IH, np.array([r]))
 
 
-@pytest.mark.parametrize("mutant", range(1, 11))
-def test_planted_mistakes_are_caught(tmp_path, mutant):
-    """Each planted mistake in the oracle (a rounding binning, a dropped or
-    sign-flipped corner term, a lost pixel, an off-by-one corner in Eq. 2, a
-    dropped row or column) must fail at least one pin."""
-    lib = oracle.compile_oracle(tmp_path / f"mut{mutant}.so", mutant=mutant)
+# Plausible mistakes, each planted into a copy of ih_oracle.c as a textual
+# patch inside one function: (function, text as written, text with the mistake).
+MISTAKES = {
+    "rounding-binning": ("ihref_Q", "return (v * B) >> 8;", "return (v * B + 128u) >> 8;"),
+    "corner-dropped": ("ihref_integral_histogram",
+                       "+ at(out, W, B, x, y - 1, b)\n                           - at(out, W, B, x - 1, y - 1, b);",
+                       "+ at(out, W, B, x, y - 1, b);"),
+    "corner-sign": ("ihref_integral_histogram", "- at(out, W, B, x - 1, y - 1, b);",
+                    "+ at(out, W, B, x - 1, y - 1, b);"),
+    "first-column-pixel-lost": ("ihref_integral_histogram", "if (q == (uint32_t)b) h += 1u;",
+                                "if (q == (uint32_t)b && x > 0) h += 1u;"),
+    "query-corner-off-by-one": ("ihref_region_histogram",
+                                "- at(Ht, W, B, x1, y0 - 1, b) + at(Ht, W, B, x0 - 1, y0 - 1, b);",
+                                "- at(Ht, W, B, x1, y0, b) + at(Ht, W, B, x0 - 1, y0, b);"),
+    "rows-corner-dropped": ("ihref_integral_rows",
+                            "const uint32_t corner = (up && x > 0) ? up[(x - 1) * B + b] : 0u;",
+                            "const uint32_t corner = 0u;"),
+    "rowdef-row-left-out": ("ihref_row_by_definition", "for (int64_t yy = 0; yy <= y; ++yy)",
+                            "for (int64_t yy = 0; yy < y; ++yy)"),
+    "count-column-left-out": ("ihref_rect_count", "for (int64_t c = x0; c <= x1; ++c)",
+                              "for (int64_t c = x0; c < x1; ++c)"),
+    "table-neighbour-entry": ("ihref_integral_histogram_lut", "const uint32_t q = lut[I[y * W + x]];",
+                              "const uint32_t q = lut[I[y * W + x] ^ 1u];"),
+    "binmajor-row-dropped": ("ihref_integral_histogram_binmajor", "for (int64_t y = 1; y < H; ++y)",
+                             "for (int64_t y = 2; y < H; ++y)"),
+    "binmajor-run-not-reset": ("ihref_integral_histogram_binmajor",
+                               "uint32_t run = 0;\n            for (int64_t x = 0; x < W; ++x) {",
+                               "uint32_t run = y > 0 ? P[y * W - 1] : 0u;\n            for (int64_t x = 0; x < W; ++x) {"),
+    "entry-column-left-out": ("ihref_entry", "for (int64_t c = 0; c <= x; ++c)", "for (int64_t c = 0; c < x; ++c)"),
+    "table-corner-sign": ("ihref_integral_histogram_lut", "- at(out, W, B, x - 1, y - 1, b);",
+                          "+ at(out, W, B, x - 1, y - 1, b);"),
+}
+
+
+def function_span(src: str, name: str):
+    """[start, end) of the body of the C function `name` in src."""
+    import re
+    m = re.search(r"^[a-z_0-9 ]*\b" + name + r"\(", src, re.M)
+    assert m, name
+    end = src.index("\n}\n", m.start()) + 3
+    return m.start(), end
+
+
+def planted_source(name: str) -> str:
+    func, old, new = MISTAKES[name]
+    src = oracle.SRC.read_text()
+    a, b = function_span(src, func)
+    body = src[a:b]
+    assert body.count(old) == 1, (name, body.count(old))
+    return src[:a] + body.replace(old, new) + src[b:]
+
+
+@pytest.mark.parametrize("name", sorted(MISTAKES))
+def test_planted_mistakes_are_caught(tmp_path, name):
+    """Each plausible mistake (a rounding binning, a dropped or sign-flipped
+    corner term, a lost pixel, an off-by-one corner in Eq. 2, a dropped row or
+    column, a wrong table entry), planted into a copy of the oracle, must fail
+    at least one pin."""
+    src = tmp_path / f"{name}.c"
+    src.write_text(planted_source(name))
+    lib = oracle.compile_oracle(tmp_path / f"{name}.so", source=src)
     fails = pin_failures(oracle.Oracle(lib), quick=True)
-    assert fails, f"mutant {mutant} passed every pin"
+    assert fails, f"planted mistake {name} passed every pin"
