@@ -3,27 +3,26 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Workload (one "step"): the 64-frame 1920x1080 moving-disc sequence with B=64
-bins (seeded synthetic stand-in for the paper's HD video), every frame's
-integral histogram computed into its own resident H x W x B uint32 tensor
-(64 x 530.8 MB = 34 GB of output per step) by ONE launch of a batched plan
-(a hipGraph holding one launch per phase for all 64 frames).  Inputs are
-resident in HBM before the timed region starts.  The same frames also go
-through a pipelined plan (4 GiB groups, each group's carry phases on a
-second stream beside the previous group's tile pass) for comparison.
+Workload (one "step"): the 256-frame uneven batch -- resolutions drawn from
+320x240 to 3840x2160 and bin counts from {16, 32, 64, 128}, uniform pixels from
+seed 3 (about 3.2e10 entries, 127 GB of uint32 output) -- every frame's
+integral histogram computed into its own resident H x W x B tensor by ONE
+launch of a batched plan (a hipGraph) whose tile shapes and carry schedules
+the autotuner chose per (H, W, B) class.  Inputs are resident in HBM before
+the timed region starts.
 
-Prints ONE JSON line: throughput (entries/s) of the batched step; the same
-frames through 64 plain per-frame ih_compute calls for comparison; the
-roofline of the dominant kernel (the tile pass, HBM-bound); the 640x480
-B=32 frame and the 8192x8192 B=128 frame through ih_compute with their
-region queries; one 1920x1080 B=64 frame in the H x W x B layout, the
-bin-major layout and with bins from a table; the host-transfer pipeline
-(frames/s with the whole integral histogram copied back over PCIe, as the
-paper measures); a device write reference (torch fill); the serving loop's
-p50/p99 latency and
-throughput on a replayed 16-stream trace next to the plain per-frame path;
-and the single-threaded CPU oracle timed on a bounded sample of the batched
-workload.
+Prints ONE JSON line: throughput (entries/s) of that step and the roofline of
+its dominant kernel, the tile pass (HBM-bound); the same frames through 256
+plain per-frame ih_compute calls; the 64-frame 1920x1080 B=64 moving-disc
+sequence through a batched plan (with its own roofline), a pipelined plan, a
+bin-major plan and the plain loop; the 640x480 B=32 frame and the 8192x8192
+B=128 frame through ih_compute with their region queries; one 1920x1080 B=64
+frame in each single-frame form; the host-transfer pipeline (frames/s with the
+whole integral histogram copied back over PCIe, as the paper measures); device
+write references (torch's fill, and the tile pass's own store stream with no
+loads); the serving loop's p50/p99 latency and throughput next to the plain
+per-frame path at several arrival rates; and the single-threaded CPU oracle
+timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -37,30 +36,38 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per tile-pass launch of the 64-frame step, from two rocprofv3 --pmc
-# runs (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the factors a 1 GiB device copy
-# reads on the same counters).  Valid only for the kernel source and tile they
-# were taken with; any other combination reports null.
-TRAFFIC_RECORD = {
-    "kernel_src_sha256": "0567a68bef331516cbc9325f68daee3086db17d778e58e6beb9ddc933c8625e9",
-    "workload": "disc_sequence_64x1080x1920_B64", "tile": [128, 216], "nontemporal": False,
-    "fetch_bytes": 336929.0 * 2.0 * 1024, "write_bytes": 33177600.0 * 1.0 * 1024,
-}
+# HBM bytes of the tile pass, from two rocprofv3 --pmc runs per workload
+# (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the factors a 1 GiB device copy
+# reads on the same counters), summed over the tile-pass dispatches of one
+# step.  Valid only for the kernel sources and schedule they were taken with;
+# any other combination reports null.
+TRAFFIC_RECORDS = {}
+
+KERNEL_SOURCES = ["ih_kernels.hip", "ih_tile.h", "ih_device.h", "ih_internal.h", "ih_tile_regular.hip",
+                  "ih_tile_regular_guarded.hip", "ih_tile_nontemporal.hip", "ih_tile_nontemporal_guarded.hip",
+                  "ih_tile_table.hip"]
 
 
-def recorded_traffic(workload: str, tile) -> float | None:
+def kernel_digest() -> str | None:
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1711_01919_amd", "csrc", "ih_kernels.hip")
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1711_01919_amd", "csrc")
     try:
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        for name in KERNEL_SOURCES:
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
-    r = TRAFFIC_RECORD
-    if (digest != r["kernel_src_sha256"] or workload != r["workload"]
-            or list(tile[:2]) != r["tile"] or bool(tile[2]) != r["nontemporal"]):
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str, schedule) -> float | None:
+    r = TRAFFIC_RECORDS.get(workload)
+    if r is None or kernel_digest() != r["kernel_sources_sha256"] or schedule != r["schedule"]:
         return None
     return r["fetch_bytes"] + r["write_bytes"]
+
+
 METRIC = "integral-hist entries/s + % HBM peak; served p50/p99 latency vs plain loop"
 
 
@@ -69,12 +76,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=64)
-    ap.add_argument("--autotune", action="store_true",
-                    help="autotune the 64-frame plan (default: the batch heuristic tile)")
-    ap.add_argument("--group-bytes", type=int, default=0,
-                    help="pipeline group size of the 64-frame plan in output bytes (<= 0: one group)")
-    ap.add_argument("--no-uneven", action="store_true", help="skip the 256-frame uneven batch leg")
+    ap.add_argument("--frames", type=int, default=64, help="frames of the moving-disc sequence leg")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline workload only (for profiling runs)")
     ap.add_argument("--no-transfer", action="store_true", help="skip the host-transfer pipeline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU-oracle sample")
@@ -102,45 +106,51 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(frames: np.ndarray, B: int, budget_s: float) -> dict:
-    """The oracle (single-threaded C, as committed) on as many frames of the
-    workload as fit in budget_s (at least one)."""
+def cpu_baseline(frames, bins, budget_s: float) -> dict:
+    """The oracle (single-threaded C, as committed) on the workload's frames in
+    order, as many as fit in budget_s (at least one); then frame-parallel on up
+    to 16 host threads for about the same time."""
     import oracle
     from oracle import _u8p, _u32p
     orc = oracle.get()
-    H, W = frames.shape[1:]
-    out = np.zeros((H, W, B), dtype=np.uint32)               # pre-faulted output
-    done, t_total = 0, 0.0
-    while done < frames.shape[0] and (done == 0 or t_total < budget_s):
+    n = len(frames)
+    done, t_total, entries = 0, 0.0, 0
+    while done < n and (done == 0 or t_total < budget_s):
         f = np.ascontiguousarray(frames[done])
+        H, W = f.shape
+        B = bins[done]
+        out = np.ones((H, W, B), dtype=np.uint32)             # pre-faulted output
         t0 = time.perf_counter()
         rc = orc.lib.ihref_integral_histogram(f.ctypes.data_as(_u8p), H, W, B, out.ctypes.data_as(_u32p))
         t_total += time.perf_counter() - t0
         assert rc == 0
+        entries += H * W * B
         done += 1
-    entries = done * H * W * B
     res = {"value": entries / t_total, "unit": "entries/s", "cores": 1, "kind": "oracle",
-           "sample": f"first {done} of {frames.shape[0]} frames ({H}x{W}, B={B}), "
+           "sample": f"first {done} of {n} frames of the workload in order ({entries:.3g} entries), "
                      f"{t_total:.1f} s single-threaded, {oracle.compile_flags()}, "
                      f"host: {os.cpu_count()} cpus, {cpu_model()}"}
     # frame-parallel, one oracle call per thread (the call releases the GIL),
-    # as the paper's multi-threaded CPU comparison
+    # as the paper's multi-threaded CPU comparison: the same sample split over
+    # the threads
     from concurrent.futures import ThreadPoolExecutor
     threads = max(1, min(16, os.cpu_count() or 1))
-    outs = [np.zeros((H, W, B), dtype=np.uint32) for _ in range(threads)]
-    per_thread = max(1, min(frames.shape[0] // threads, int(budget_s / max(t_total / done, 1e-9))))
+    sample = list(range(done)) * max(1, threads // max(done, 1))
 
-    def work(t):
-        for k in range(per_thread):
-            f = np.ascontiguousarray(frames[(t * per_thread + k) % frames.shape[0]])
-            assert orc.lib.ihref_integral_histogram(f.ctypes.data_as(_u8p), H, W, B,
-                                                    outs[t].ctypes.data_as(_u32p)) == 0
+    def work(k):
+        f = np.ascontiguousarray(frames[k])
+        H, W = f.shape
+        out = np.ones((H, W, bins[k]), dtype=np.uint32)
+        t0 = time.perf_counter()
+        assert orc.lib.ihref_integral_histogram(f.ctypes.data_as(_u8p), H, W, bins[k],
+                                                out.ctypes.data_as(_u32p)) == 0
+        return H * W * bins[k], time.perf_counter() - t0
     t0 = time.perf_counter()
     with ThreadPoolExecutor(threads) as ex:
-        list(ex.map(work, range(threads)))
+        got = list(ex.map(work, sample))
     t_par = time.perf_counter() - t0
-    res["parallel"] = {"value": threads * per_thread * H * W * B / t_par, "cores": threads,
-                       "sample": f"{threads} threads x {per_thread} frames, {t_par:.1f} s"}
+    res["parallel"] = {"value": sum(e for e, _ in got) / t_par, "cores": threads,
+                       "sample": f"{len(sample)} frames over {threads} threads, {t_par:.1f} s"}
     return res
 
 
@@ -248,18 +258,33 @@ def plain_and_query_legs(torch, ihb, synth, stream) -> dict:
     return out
 
 
-def device_reference(torch) -> dict:
+def device_reference(torch, ihb) -> dict:
     """What plain device writes reach on this GPU: torch's fill of 8 GiB and
-    of 32 GiB (write-only streams).  Boxes of the same model differ by tens
-    of percent, so the integral-histogram figures are best read next to these."""
+    of 32 GiB (write-only streams, one chunk of addresses after another), and
+    the tile pass's own store stream with no loads and no arithmetic
+    (ih_write_reference) in the moving-disc sequence's geometry: 64 frames of
+    1080 x 1920 x 64 stacked into one 69120 x 1920 x 64 tensor (34 GB), tiles
+    of 128 x 216, the same work items and store order as that batch's tile
+    pass.  Boxes of the same model differ by tens of percent, so the
+    integral-histogram figures are best read next to these."""
     res = {}
+    stream = torch.cuda.current_stream()
     for gib in (8, 32):
         x = torch.empty(gib << 30, dtype=torch.uint8, device="cuda")
         x.fill_(1)
-        ms = timed(torch, torch.cuda.current_stream(), lambda: x.fill_(7), 5) / 5
+        ms = timed(torch, stream, lambda: x.fill_(7), 5) / 5
         res[f"fill_{gib}GiB_gbs"] = (gib << 30) / (ms / 1e3) / 1e9
         del x
         torch.cuda.empty_cache()
+    H, W, B = 64 * 1080, 1920, 64
+    out = torch.empty((H, W, B), dtype=torch.uint32, device="cuda")
+    ihb.write_reference(out, (128, 216), stream)
+    torch.cuda.synchronize()
+    assert int(out[H - 1, W - 1, B - 1]) == H - 1 and int(out[0, 0, 0]) == 0
+    ms = timed(torch, stream, lambda: ihb.write_reference(out, (128, 216), stream), 5) / 5
+    res["tile_geometry_write_64x1080x1920_B64_128x216_gbs"] = H * W * B * 4 / (ms / 1e3) / 1e9
+    del out
+    torch.cuda.empty_cache()
     return res
 
 
@@ -294,10 +319,35 @@ def transfer_leg(torch, ihb) -> dict:
     return res
 
 
-def uneven_leg(torch, ihb, synth, stream) -> dict:
-    """256 frames of five resolutions and four bin counts (seed 3) through one
-    autotuned batched plan (one graph launch), against 256 plain ih_compute
-    calls on the same buffers."""
+def schedule_summary(plan, frames, bins):
+    """Per (H, W, B) class: the tile, store flavour and carry schedule the plan
+    chose (one entry per class; every frame of a class gets the same)."""
+    seen = {}
+    for k, (f, b) in enumerate(zip(frames, bins)):
+        key = f"{f.shape[0]}x{f.shape[1]} B{b}"
+        if key not in seen:
+            sc = plan.frame_schedule(k)
+            seen[key] = (f"{sc['tile'][0]}x{sc['tile'][1]}" + (" nt" if sc["nontemporal"] else "") +
+                         (f" fused K={sc['carry_bands']}" if sc["carry_bands"] else " reduce-then-scan"))
+    return dict(sorted(seen.items()))
+
+
+def profiled_steps(torch, stream, plan, ihb, steps):
+    """K plan launches with the per-phase event profiler on: HIP events on the
+    launch stream bracket each phase's graph (every tile-pass launch of the
+    step lies inside the tile phase's pair)."""
+    ihb.profile_enable(True)
+    ms = timed(torch, stream, lambda: plan.launch(stream), steps)
+    ph = ihb.profile_read()
+    ihb.profile_enable(False)
+    return ms, ph
+
+
+def uneven_headline(torch, ihb, synth, stream, args) -> dict:
+    """The headline: 256 frames of five resolutions and four bin counts (seed
+    3) through one autotuned batched plan, one graph launch per step; then
+    the same frames through 256 plain ih_compute calls on the same buffers."""
+    import oracle
     ub = synth.uneven_batch()
     fr = [torch.from_numpy(f).cuda() for f in ub.frames]
     outs = [torch.empty((f.shape[0], f.shape[1], b), dtype=torch.uint32, device="cuda")
@@ -305,26 +355,117 @@ def uneven_leg(torch, ihb, synth, stream) -> dict:
     t0 = time.time()
     plan = ihb.BatchPlan(fr, outs, ub.bins, autotune=True, stream=stream)
     tune_s = time.time() - t0
-    plan.launch(stream)
-    ms = timed(torch, stream, lambda: plan.launch(stream), 3) / 3
-    tiles = sorted({(f.shape[0], f.shape[1], b) + plan.frame_tile(k)
-                    for k, (f, b) in enumerate(zip(ub.frames, ub.bins))})
+    info = plan.info()
+    sched = schedule_summary(plan, ub.frames, ub.bins)
+    log(f"[bench] uneven batch plan in {tune_s:.1f}s: {info}")
+    for _ in range(args.warmup):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    ms_total = timed(torch, stream, lambda: plan.launch(stream), args.steps)
+    ms_prof, ph = profiled_steps(torch, stream, plan, ihb, args.steps)
+    ms = ms_total / args.steps
+    log(f"[bench] uneven batch: {ms:.3f} ms/step; profiled {ms_prof / args.steps:.3f} ms/step, phases {ph}")
+    # parity spot check of the timed outputs: the last row of a few frames
+    orc = oracle.get()
+    for k in (0, 1, 127, 255):
+        H = ub.frames[k].shape[0]
+        assert np.array_equal(outs[k][H - 1].cpu().numpy(), orc.row_by_definition(ub.frames[k], ub.bins[k], H - 1)), \
+            f"uneven batch parity spot check failed ({k})"
 
     def plain():
         for k, b in enumerate(ub.bins):
             ihb.compute(fr[k], b, out=outs[k], stream=stream)
     plain()
     ms_plain = timed(torch, stream, plain, 3) / 3
-    info = plan.info()
     plan.close()
     del plan, plain, fr, outs
     torch.cuda.empty_cache()
     ent = ub.entries
-    return {"frames": len(ub.frames), "entries": ent, "ms_per_launch": ms, "entries_per_s": ent / (ms / 1e3),
-            "hbm_frac": (4 * ent + sum(f.size for f in ub.frames)) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "plain_loop_ms": ms_plain, "speedup_batched": ms_plain / ms, "autotune_s": tune_s,
-            "kernel_launches": info["kernel_launches"],
-            "tiles": [f"{h}x{w} B{b}: {tx}x{ty}{' nt' if nt else ''}" for h, w, b, tx, ty, nt in tiles]}
+    alg = 4 * ent + sum(f.size for f in ub.frames)
+    tile_ms = ph["tile_ms"] / args.steps                      # tile-pass kernels of one step, back to back
+    achieved = alg / (tile_ms / 1e3) / 1e9
+    return {"frames": len(ub.frames), "entries": ent, "alg_bytes": alg, "ms_per_step": ms,
+            "entries_per_s": ent / (ms / 1e3), "hbm_frac_step": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "profiled_ms_per_step": ms_prof / args.steps,
+            "phase_ms_per_step": {k: ph[k] / args.steps for k in ("agg_ms", "scan_ms", "tile_ms")},
+            "plain_loop": {"ms_per_step": ms_plain, "entries_per_s": ent / (ms_plain / 1e3),
+                           "speedup_batched": ms_plain / ms},
+            "autotune_s": tune_s, "kernel_launches": info["kernel_launches"],
+            "tile_launches": info["tile_launches"], "schedules": sched,
+            "roofline": {"bound": "hbm", "kernel": "tile_batch_kernel (all variants of the step)",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": recorded_traffic("uneven_batch_256", sched),
+                         "alg_bytes_per_step": alg, "tile_launches_per_step": info["tile_launches"],
+                         "tile_ms_per_step": tile_ms}}
+
+
+def disc_sequence_leg(torch, ihb, synth, stream, args) -> dict:
+    """The 64-frame 1920x1080 B=64 moving-disc sequence: one batched plan
+    (heuristic tiles, one graph launch), the plain per-frame loop, a
+    pipelined plan (4 GiB groups) and a plan writing the bin-major layout."""
+    import oracle
+    frames, B = synth.disc_sequence(n_frames=args.frames)
+    n, H, W = frames.shape
+    d_frames = torch.from_numpy(frames).cuda()
+    outs = [torch.empty((H, W, B), dtype=torch.uint32, device="cuda") for _ in range(n)]
+    plan = ihb.BatchPlan([d_frames[k] for k in range(n)], outs, [B] * n, stream=stream)
+    tile = plan.frame_tile(0)
+    sched = schedule_summary(plan, list(frames), [B] * n)
+    info = plan.info()
+    for _ in range(args.warmup):
+        plan.launch(stream)
+    ms_total = timed(torch, stream, lambda: plan.launch(stream), args.steps)
+    ms_prof, ph = profiled_steps(torch, stream, plan, ihb, args.steps)
+    ms_step = ms_total / args.steps
+    entries_step = n * H * W * B
+    alg = n * (H * W + 4 * H * W * B)
+    orc = oracle.get()
+    for k in (0, n - 1):
+        assert np.array_equal(outs[k][H - 1].cpu().numpy(), orc.row_by_definition(frames[k], B, H - 1)), k
+
+    def plain_step():
+        for k in range(n):
+            ihb.compute(d_frames[k], B, out=outs[k], stream=stream)
+    plain_step()
+    plain_steps = max(2, min(args.steps, 10))
+    ms_plain = timed(torch, stream, plain_step, plain_steps) / plain_steps
+    pplan = ihb.BatchPlan([d_frames[k] for k in range(n)], outs, [B] * n, stream=stream, group_bytes=4 << 30)
+    pinfo = pplan.info()
+    for _ in range(max(1, args.warmup)):
+        pplan.launch(stream)
+    ms_pipe = timed(torch, stream, lambda: pplan.launch(stream), args.steps) / args.steps
+    pplan.close()
+    bplan = ihb.BatchPlan([d_frames[k] for k in range(n)], [o.view(B, H, W) for o in outs], [B] * n,
+                          stream=stream, binmajor=[True] * n)
+    bplan.launch(stream)
+    torch.cuda.synchronize()
+    got = outs[n - 1].view(B, H, W)[:, H - 1].cpu().numpy().T
+    assert np.array_equal(got, orc.row_by_definition(frames[n - 1], B, H - 1)), "bin-major spot check failed"
+    ms_bm = timed(torch, stream, lambda: bplan.launch(stream), args.steps) / args.steps
+    bm_tile = list(bplan.frame_tile(0)[:2])
+    bplan.close()
+    plan.close()
+    del outs, plan, d_frames
+    torch.cuda.empty_cache()
+    tile_ms = ph["tile_ms"] / args.steps
+    achieved = alg / (tile_ms / 1e3) / 1e9
+    return {"workload": f"disc_sequence_{n}x{H}x{W}_B{B}", "ms_per_step": ms_step,
+            "entries_per_s": entries_step / (ms_step / 1e3), "hbm_frac_step": alg / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "tile": list(tile[:2]), "schedules": sched, "kernel_launches": info["kernel_launches"],
+            "profiled_ms_per_step": ms_prof / args.steps,
+            "phase_ms_per_step": {k: ph[k] / args.steps for k in ("agg_ms", "scan_ms", "tile_ms")},
+            "plain_loop": {"ms_per_step": ms_plain, "entries_per_s": entries_step / (ms_plain / 1e3),
+                           "speedup_batched": ms_plain / ms_step},
+            "pipelined_4GiB": {"ms_per_step": ms_pipe, "entries_per_s": entries_step / (ms_pipe / 1e3),
+                               "groups": pinfo["groups"]},
+            "binmajor_batched": {"ms_per_step": ms_bm, "entries_per_s": entries_step / (ms_bm / 1e3),
+                                 "hbm_frac": alg / (ms_bm / 1e3) / 1e9 / HBM_PEAK_GBS, "tile": bm_tile},
+            "roofline": {"bound": "hbm", "kernel": "tile_batch_kernel", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": recorded_traffic(f"disc_sequence_{n}x{H}x{W}_B{B}", sched),
+                         "alg_bytes_per_step": alg, "tile_launches_per_step": info["tile_launches"],
+                         "tile_ms_per_step": tile_ms}}
 
 
 def percentiles(xs):
@@ -426,140 +567,44 @@ def main():
         return
     from paper_1711_01919_amd import binding as ihb
     from paper_1711_01919_amd import synth
-    import oracle
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    t0 = time.time()
-    frames, B = synth.disc_sequence(n_frames=args.frames)
-    n, H, W = frames.shape
-    log(f"[bench] generated {n} frames {H}x{W} B={B} in {time.time() - t0:.1f}s")
-
-    d_frames = torch.from_numpy(frames).to(dev)
-    outs = [torch.empty((H, W, B), dtype=torch.uint32, device=dev) for _ in range(n)]
     stream = torch.cuda.current_stream()
 
-    t0 = time.time()
-    plan = ihb.BatchPlan([d_frames[k] for k in range(n)], outs, [B] * n,
-                         autotune=args.autotune, stream=stream, group_bytes=args.group_bytes)
-    tile = plan.frame_tile(0)
-    info = plan.info()
-    log(f"[bench] plan ready in {time.time() - t0:.1f}s: tile {tile}, {info}")
+    head = uneven_headline(torch, ihb, synth, stream, args)
+    if args.only_headline:
+        legs = {}
+    else:
+        legs = {"disc_sequence_64x1080x1920_B64": disc_sequence_leg(torch, ihb, synth, stream, args)}
+        log(f"[bench] disc sequence: {legs['disc_sequence_64x1080x1920_B64']}")
+        legs.update(plain_and_query_legs(torch, ihb, synth, stream))
+        log("[bench] plain/query legs done")
+        if not args.no_transfer:
+            legs["transfer_pipeline"] = transfer_leg(torch, ihb)
+            log(f"[bench] transfer pipeline: {legs['transfer_pipeline']}")
+        torch.cuda.empty_cache()
+        legs["device_reference"] = device_reference(torch, ihb)
+        log(f"[bench] device reference: {legs['device_reference']}")
+        if args.serve_seconds > 0:
+            legs["serving"] = serving_leg(torch, ihb, synth, args.serve_seconds)
+            log(f"[bench] serving: {legs['serving']}")
 
-    for _ in range(args.warmup):
-        plan.launch(stream)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps)")
-
-    # timed region: K plan launches exactly as a caller makes them (one graph
-    # launch each), then K more with the per-phase event profiler on, which
-    # brackets every tile-pass launch with HIP events on its own stream
-    ms_total = timed(torch, stream, lambda: plan.launch(stream), args.steps)
-    ihb.profile_enable(True)
-    ms_prof = timed(torch, stream, lambda: plan.launch(stream), args.steps)
-    ph = ihb.profile_read()
-    ihb.profile_enable(False)
-    log(f"[bench] timed {args.steps} batched steps: {ms_total:.2f} ms; profiled: {ms_prof:.2f} ms, phases {ph}")
-
-    ms_step = ms_total / args.steps
-    entries_step = n * H * W * B
-    alg_bytes_frame = H * W + 4 * H * W * B                   # frame read + output written
-    value = entries_step / (ms_step / 1e3)
-    launches = args.steps * info["tile_launches"]             # tile-pass kernels in the profiled steps
-    tile_ms_launch = ph["tile_ms"] / launches
-    alg_bytes_launch = n * alg_bytes_frame / info["tile_launches"]
-    achieved = alg_bytes_launch / (tile_ms_launch / 1e3) / 1e9
-    step_gbs = n * alg_bytes_frame / (ms_step / 1e3) / 1e9
-
-    # parity spot check of the timed outputs: last row of first and last frame
-    orc = oracle.get()
-    for k in (0, n - 1):
-        got = outs[k][H - 1].cpu().numpy()
-        assert np.array_equal(got, orc.row_by_definition(frames[k], B, H - 1)), f"parity spot check failed ({k})"
-
-    # the same frames through the plain per-frame loop
-    def plain_step():
-        for k in range(n):
-            ihb.compute(d_frames[k], B, out=outs[k], stream=stream)
-    plain_step()
-    plain_steps = max(2, min(args.steps, 10))
-    ms_plain = timed(torch, stream, plain_step, plain_steps) / plain_steps
-    log(f"[bench] plain loop: {ms_plain:.3f} ms/step")
-
-    # the same frames through a pipelined plan (4 GiB groups, carries of the
-    # next group on a second stream)
-    pplan = ihb.BatchPlan([d_frames[k] for k in range(n)], outs, [B] * n, stream=stream,
-                          group_bytes=4 << 30)
-    pinfo = pplan.info()
-    for _ in range(max(1, args.warmup)):
-        pplan.launch(stream)
-    ms_pipe = timed(torch, stream, lambda: pplan.launch(stream), args.steps) / args.steps
-    pipelined = {"ms_per_step": ms_pipe, "value": entries_step / (ms_pipe / 1e3), "groups": pinfo["groups"],
-                 "tile": list(pplan.frame_tile(0))}
-    pplan.close()
-    log(f"[bench] pipelined plan: {pipelined}")
-
-    # the same frames with bin-major outputs (the paper's b x h x w layout),
-    # one plan over the same buffers viewed as (B, H, W)
-    bplan = ihb.BatchPlan([d_frames[k] for k in range(n)], [o.view(B, H, W) for o in outs], [B] * n,
-                          stream=stream, binmajor=[True] * n)
-    bplan.launch(stream)
-    torch.cuda.synchronize()
-    got = outs[n - 1].view(B, H, W)[:, H - 1].cpu().numpy().T
-    assert np.array_equal(got, orc.row_by_definition(frames[n - 1], B, H - 1)), "bin-major spot check failed"
-    ms_bm = timed(torch, stream, lambda: bplan.launch(stream), args.steps) / args.steps
-    binmajor = {"ms_per_step": ms_bm, "value": entries_step / (ms_bm / 1e3),
-                "hbm_frac": n * alg_bytes_frame / (ms_bm / 1e3) / 1e9 / HBM_PEAK_GBS,
-                "tile": list(bplan.frame_tile(0)[:2])}
-    bplan.close()
-    log(f"[bench] bin-major plan: {binmajor}")
-
-
-    plan.close()
-    del outs, plan
-    torch.cuda.empty_cache()
-    legs = plain_and_query_legs(torch, ihb, synth, stream)
-    log(f"[bench] plain/query legs: {legs}")
-    if not args.no_uneven:
-        legs["uneven_batch_256"] = uneven_leg(torch, ihb, synth, stream)
-        log(f"[bench] uneven batch: {legs['uneven_batch_256']}")
-    if not args.no_transfer:
-        legs["transfer_pipeline"] = transfer_leg(torch, ihb)
-        log(f"[bench] transfer pipeline: {legs['transfer_pipeline']}")
-    served = None
-    torch.cuda.empty_cache()
-    legs["device_reference"] = device_reference(torch)
-    log(f"[bench] device reference: {legs['device_reference']}")
-    if args.serve_seconds > 0:
-        served = serving_leg(torch, ihb, synth, args.serve_seconds)
-        log(f"[bench] serving: {served}")
-
+    ms_step = head["ms_per_step"]
     rec = {
-        "metric": METRIC, "value": value, "unit": "entries/s",
+        "metric": METRIC, "value": head["entries_per_s"], "unit": "entries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"disc_sequence_{n}x{H}x{W}_B{B}", "frames": n, "H": H, "W": W, "B": B,
-                   "form": "batched_graph", "tile": list(tile[:2]), "nontemporal": tile[2],
-                   "pipeline_groups": info["groups"], "parallelism": "single_gpu"},
-        "hbm_frac_step": step_gbs / HBM_PEAK_GBS,
-        "plain_loop": {"value": entries_step / (ms_plain / 1e3), "ms_per_step": ms_plain,
-                       "speedup_batched": ms_plain / ms_step},
-        "profiled_ms_per_step": ms_prof / args.steps,
-        "pipelined_4GiB": pipelined,
-        "binmajor_batched": binmajor,
-        "phase_ms_per_step": {k: ph[k] / args.steps for k in ("agg_ms", "scan_ms", "tile_ms")},
-        "roofline": {"bound": "hbm", "kernel": "tile_batch_kernel", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic(f"disc_sequence_{n}x{H}x{W}_B{B}", tile),
-                     "alg_bytes_per_launch": alg_bytes_launch,
-                     "launches": launches, "avg_launch_us": tile_ms_launch * 1e3},
+        "config": {"workload": "uneven_batch_256", "frames": head["frames"], "entries": head["entries"],
+                   "resolutions": "320x240..3840x2160 (seed 3)", "bins": "16/32/64/128",
+                   "form": "batched_graph_autotuned", "parallelism": "single_gpu"},
+        "roofline": head.pop("roofline"),
+        "uneven_batch_256": head,
     }
     rec.update(legs)
-    if served is not None:
-        rec["serving"] = served
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(frames, B, args.cpu_seconds)
+        ub = synth.uneven_batch()
+        rec["cpu_baseline"] = cpu_baseline(ub.frames, ub.bins, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 
 

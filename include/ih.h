@@ -187,7 +187,24 @@ typedef struct {
                                while the previous group's tile pass runs, so the
                                tile pass finds them in cache.  <= 0: one group,
                                all phases in order (default)                     */
+    int32_t carry_bands;    /* carry schedule.  -1: as chosen (heuristic, or
+                               autotuned per class); 0: reduce-then-scan (a count
+                               launch, two scan launches, the tile pass); K >= 1:
+                               fused -- the count launch counts bands of K tile
+                               bands and scans the carries itself, so the tile
+                               pass follows it directly (K is clamped to a frame's
+                               band count; frames whose geometry cannot take it,
+                               and bin-major frames, keep reduce-then-scan)      */
 } ih_batch_options;
+
+/* The schedule a plan chose for one frame. */
+typedef struct {
+    int32_t tile_x, tile_y;     /* tile: columns x rows                             */
+    int32_t nontemporal;        /* 1: non-temporal output stores                    */
+    int32_t carry_bands;        /* 0: reduce-then-scan; K >= 1: fused, K tile bands
+                                   per carry band                                   */
+    int32_t group;              /* pipeline group of the frame (0 when one group)   */
+} ih_frame_schedule;
 
 typedef struct ih_batch_plan ih_batch_plan;
 
@@ -221,7 +238,8 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
  * repeatedly; launches of one plan on different streams must not overlap. */
 ih_status ih_batch_plan_launch(ih_batch_plan* plan, ih_stream_t stream);
 
-/* Synchronizes the device, then frees the plan's scratch, tables and graphs. */
+/* Waits for the plan's last launch and for its creation stream (nothing
+ * else), then frees the plan's scratch, tables and graphs. */
 ih_status ih_batch_plan_destroy(ih_batch_plan* plan);
 
 ih_status ih_batch_plan_info(const ih_batch_plan* plan, ih_batch_info* info);
@@ -230,6 +248,11 @@ ih_status ih_batch_plan_info(const ih_batch_plan* plan, ih_batch_info* info);
 ih_status ih_batch_plan_frame_tile(const ih_batch_plan* plan, size_t k, int32_t* tile_x,
                                    int32_t* tile_y, int32_t* nontemporal);
 
+/* The whole schedule chosen for frame k of the plan: tile, store flavour,
+ * carry schedule and pipeline group (Sec. 3.5 weighs carry schedules for the
+ * tiled scans; these are this library's). */
+ih_status ih_batch_plan_frame_schedule(const ih_batch_plan* plan, size_t k, ih_frame_schedule* sched);
+
 /* ---------------------------------------------------------------------------
  * Host-transfer pipeline (Sec. 4.4, Algorithm 6): frames in host memory, whole
  * integral histograms back to host memory, copies and kernels of consecutive
@@ -237,24 +260,28 @@ ih_status ih_batch_plan_frame_tile(const ih_batch_plan* plan, size_t k, int32_t*
  * ------------------------------------------------------------------------- */
 
 typedef struct {
-    double wall_ms;        /* earliest upload start to latest download end        */
+    double wall_ms;        /* first upload start to last download end             */
     double frames_per_s;   /* frames / wall                                        */
     double h2d_ms;         /* per-stage sums over frames, each stage timed on its  */
-    double kernel_ms;      /* own stream (a stage that waits for the device to     */
-    double d2h_ms;         /* free up counts the wait)                             */
+    double kernel_ms;      /* own stream (uploads and kernels on one, downloads on */
+    double d2h_ms;         /* the other)                                           */
 } ih_pipeline_stats;
 
 /*
  * ih_transfer_pipeline -- for k in [0, n): upload frames_host[k] (H*W uint8),
  * compute its integral histogram (Sec. 2.1 Eq. 1; same kernels and tile as
- * ih_compute) and download all H*W*B uint32 of it to outs_host[k].  Frame k
- * runs on stream k mod n_streams (n_streams in [1, 8]; 2 is the paper's double
- * buffering), each stream with its own device buffers, so one frame's download
- * overlaps the next frames' uploads and kernels.  Host buffers are the
- * caller's; pinned ones (hipHostMalloc) move at full link speed, pageable ones
- * are staged by the runtime.  Output buffers must not alias.  Blocking: returns
- * when every output is in host memory; device buffers are allocated and freed
- * by the call.  stats may be NULL (then no events are recorded).
+ * ih_compute) and download all H*W*B uint32 of it to outs_host[k].  The
+ * device holds n_streams buffer slots (1..8; 2 is the paper's double
+ * buffering); frame k uses slot k mod n_streams.  Uploads and kernels run in
+ * frame order on one stream, downloads in frame order on another, so one
+ * frame's download overlaps the next frames' uploads and kernels while the
+ * device-to-host link carries one download at a time; a slot is reused once
+ * its previous frame's download has finished.  Host buffers are the caller's;
+ * pinned ones (hipHostMalloc) move at full link speed, pageable ones are
+ * staged by the runtime.  Output buffers must not alias.  Blocking: returns
+ * when every output is in host memory; device buffers and streams are
+ * allocated and freed by the call.  stats may be NULL (then no timing events
+ * are recorded).
  * Errors: IH_ERR_INVALID_ARG (null pointer, n == 0, bad shape or n_streams),
  * IH_ERR_RANGE, IH_ERR_OOM, IH_ERR_HIP.
  */
@@ -370,6 +397,18 @@ typedef struct {
 
 ih_status ih_profile_enable(int on);
 ih_status ih_profile_read(ih_phase_times* t);
+
+/*
+ * ih_write_reference -- for measurement only: writes an H x W x B uint32
+ * tensor (device, layout above; each entry gets its row index) with the
+ * tile pass's work items, lanes and store order for a tile_x x tile_y tile,
+ * but no loads and no arithmetic.  The time it takes is what the device's
+ * write path allows the tile pass in that geometry.  B <= 64; tile_x in
+ * {32, 64, 128}; tile_y >= 1.  Asynchronous on stream.
+ * Errors: IH_ERR_INVALID_ARG, IH_ERR_RANGE, IH_ERR_HIP.
+ */
+ih_status ih_write_reference(uint32_t* out, int32_t H, int32_t W, int32_t B, int32_t tile_x, int32_t tile_y,
+                             ih_stream_t stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* ih_status_str(ih_status s);

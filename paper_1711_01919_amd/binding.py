@@ -52,7 +52,13 @@ class FrameDesc(ctypes.Structure):
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("group_bytes", ctypes.c_int64)]
+                ("tile_y", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("group_bytes", ctypes.c_int64),
+                ("carry_bands", ctypes.c_int32)]
+
+
+class FrameSchedule(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("carry_bands", ctypes.c_int32), ("group", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -88,6 +94,8 @@ def _load() -> ctypes.CDLL:
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     lib.ih_compute.argtypes = [vp, i32, i32, i32, vp, vp]
     lib.ih_compute_binmajor.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.ih_write_reference.argtypes = [vp, i32, i32, i32, i32, i32, vp]
+    lib.ih_write_reference.restype = ctypes.c_int
     lib.ih_compute_binmajor.restype = ctypes.c_int
     lib.ih_compute_lut.argtypes = [vp, i32, i32, i32, vp, vp, vp]
     lib.ih_compute_lut.restype = ctypes.c_int
@@ -109,8 +117,9 @@ def _load() -> ctypes.CDLL:
     lib.ih_batch_plan_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
     lib.ih_batch_plan_frame_tile.argtypes = [vp, sz, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                              ctypes.POINTER(i32)]
+    lib.ih_batch_plan_frame_schedule.argtypes = [vp, sz, ctypes.POINTER(FrameSchedule)]
     for f in (lib.ih_batch_plan_create, lib.ih_batch_plan_launch, lib.ih_batch_plan_destroy,
-              lib.ih_batch_plan_info, lib.ih_batch_plan_frame_tile):
+              lib.ih_batch_plan_info, lib.ih_batch_plan_frame_tile, lib.ih_batch_plan_frame_schedule):
         f.restype = ctypes.c_int
     lib.ih_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.ih_submit.argtypes = [vp, i32, vp, i32, i32, i32, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
@@ -200,6 +209,15 @@ def compute_lut(frame: torch.Tensor, B: int, lut, out: torch.Tensor | None = Non
     return out
 
 
+def write_reference(out: torch.Tensor, tile, stream=None) -> None:
+    """ih_write_reference on an (H, W, B) uint32 device tensor (B <= 64)."""
+    if out.dtype != torch.uint32 or out.dim() != 3 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous (H, W, B) uint32 CUDA tensor")
+    H, W, B = out.shape
+    _check(lib.ih_write_reference(_ptr(out), H, W, B, int(tile[0]), int(tile[1]), _stream_handle(stream)),
+           "ih_write_reference")
+
+
 def compute_raw(frame_ptr: int, H: int, W: int, B: int, out_ptr: int, stream=None) -> int:
     """Direct pass-through of ih_compute (status code returned, not raised)."""
     return lib.ih_compute(frame_ptr, H, W, B, out_ptr, _stream_handle(stream))
@@ -277,11 +295,13 @@ class BatchPlan:
     keeps references to them."""
 
     def __init__(self, frames, outs, bins, autotune=False, use_graph=True, tile=None,
-                 nontemporal=-1, stream=None, group_bytes=0, luts=None, binmajor=None):
+                 nontemporal=-1, stream=None, group_bytes=0, luts=None, binmajor=None, carry_bands=-1):
         """group_bytes > 0 pipelines the plan in groups of about that many
         output bytes (see ih_batch_options in include/ih.h).  luts: None, or
         per frame None (uniform bins) or a 256-entry bin table.  binmajor:
-        None, or per frame whether its output takes the (B, H, W) layout."""
+        None, or per frame whether its output takes the (B, H, W) layout.
+        carry_bands: -1 as chosen, 0 reduce-then-scan, K >= 1 the fused carry
+        schedule with K tile bands per carry band."""
         if not (len(frames) == len(outs) == len(bins)) or len(frames) == 0:
             raise ValueError("frames, outs and bins must be equally long and non-empty")
         tables = [None] * len(frames) if luts is None else [
@@ -302,7 +322,7 @@ class BatchPlan:
                                  None if tables[k] is None else tables[k].ctypes.data, 1 if layouts[k] else 0)
         tx, ty = tile if tile else (0, 0)
         opt = BatchOptions(1 if autotune else 0, 1 if use_graph else 0, tx, ty, int(nontemporal),
-                           int(group_bytes))
+                           int(group_bytes), int(carry_bands))
         h = ctypes.c_void_p()
         _check(lib.ih_batch_plan_create(descs, len(frames), ctypes.byref(opt), _stream_handle(stream),
                                         ctypes.byref(h)), "ih_batch_plan_create")
@@ -323,6 +343,12 @@ class BatchPlan:
         _check(lib.ih_batch_plan_frame_tile(self._h, k, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(nt)),
                "ih_batch_plan_frame_tile")
         return tx.value, ty.value, bool(nt.value)
+
+    def frame_schedule(self, k: int) -> dict:
+        sc = FrameSchedule()
+        _check(lib.ih_batch_plan_frame_schedule(self._h, k, ctypes.byref(sc)), "ih_batch_plan_frame_schedule")
+        return {"tile": (sc.tile_x, sc.tile_y), "nontemporal": bool(sc.nontemporal),
+                "carry_bands": sc.carry_bands, "group": sc.group}
 
     def close(self):
         if self._h:

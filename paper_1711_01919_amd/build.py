@@ -33,6 +33,11 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 
 SOURCES = {
     "ih_kernels.hip": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_tile_regular.hip": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_tile_regular_guarded.hip": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_tile_nontemporal.hip": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_tile_nontemporal_guarded.hip": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_tile_table.hip": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_capi.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_batch.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_util.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
@@ -40,6 +45,7 @@ SOURCES = {
     "ih_server.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_pipeline.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
     "ih_geom.cpp": ["-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS],
+    "ih_admission.cpp": [],
 }
 
 

@@ -32,6 +32,7 @@ using ih::hip_fail;
 struct PlanGroup {
     ih::BatchImage image;
     size_t dev_off = 0;         // byte offset of the image in the plan's device tables
+    size_t frames = 0;          // consecutive frames of the plan in this group
 };
 
 struct ih_batch_plan {
@@ -53,6 +54,9 @@ struct ih_batch_plan {
     hipGraphExec_t exec_all = nullptr;
     hipGraphExec_t exec_phase[ih::kNumPhases] = {nullptr, nullptr, nullptr};
     int64_t entries = 0;
+    hipStream_t stream = nullptr;         // creation stream (clears scratch, runs the autotuner)
+    hipEvent_t ev_done = nullptr;         // recorded after each launch; destroy waits for it
+    bool launched = false;
 };
 
 namespace {
@@ -103,6 +107,7 @@ void free_plan(ih_batch_plan* p)
     for (hipEvent_t e : p->ev_carry) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->ev_tile) (void)hipEventDestroy(e);
     if (p->ev_start) (void)hipEventDestroy(p->ev_start);
+    if (p->ev_done) (void)hipEventDestroy(p->ev_done);
     if (p->side) (void)hipStreamDestroy(p->side);
     if (p->d_image) (void)hipFree(p->d_image);
     if (p->d_luts) (void)hipFree(p->d_luts);
@@ -138,6 +143,11 @@ ih_status build_plan(ih_batch_plan* p)
         (void)hipGetLastError();
         return fail(IH_ERR_OOM, "batch scratch of %zu bytes: %s", words * 4, hipGetErrorString(e));
     }
+    // arrival counters of fused frames start at zero (and are zero again
+    // after every launch)
+    e = hipMemsetAsync(p->d_scratch, 0, std::max<size_t>(words * 4, 256), p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "clear batch scratch");
     if (!p->luts.empty()) {
         e = hipMalloc(&p->d_luts, p->luts.size());
         if (e != hipSuccess) {
@@ -186,6 +196,7 @@ ih_status build_plan(ih_batch_plan* p)
         std::vector<ih::FrameArgs> sub(frames.begin() + k0, frames.begin() + k1);
         std::vector<char> subnt(nt.begin() + k0, nt.begin() + k1), subbm(bm.begin() + k0, bm.begin() + k1);
         ih::build_batch_image(sub, subnt, &G.image, true, &subbm);
+        G.frames = k1 - k0;
         G.dev_off = bytes;
         bytes = ih::align_up(bytes + G.image.bytes(), 256);
         p->groups.push_back(std::move(G));
@@ -264,7 +275,11 @@ TuneCache& tune_cache()
 
 const char* cache_path() { return std::getenv("IH_AUTOTUNE_CACHE"); }
 
-// The cache file holds one line per class: "gfx950 H W B NB TX TY NT".
+// The cache file holds one line per class: "gfx950/2 H W B NB TX TY NT K"
+// (K: tile bands per carry band of the fused schedule, 0 for
+// reduce-then-scan).  Lines of any other tag are skipped.
+constexpr const char* kCacheTag = "gfx950/2";
+
 void load_cache(TuneCache& c)
 {
     if (c.loaded) return;
@@ -272,12 +287,17 @@ void load_cache(TuneCache& c)
     const char* path = cache_path();
     if (!path) return;
     std::ifstream in(path);
-    std::string arch;
-    int H, W, B, NB, TX, TY, NT;
-    while (in >> arch >> H >> W >> B >> NB >> TX >> TY >> NT) {
-        if (arch != "gfx950") continue;
-        ih::TileChoice t{TX, TY, NT != 0};
-        if (ih::tile_supported(B, t)) c.best[TuneKey{H, W, B, NB}] = t;
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string tag;
+        int H, W, B, NB, TX, TY, NT, K;
+        if (!(ls >> tag >> H >> W >> B >> NB >> TX >> TY >> NT >> K) || tag != kCacheTag) continue;
+        if (H < 1 || W < 1 || B < 1 || B > 256 || K < 0) continue;
+        ih::TileChoice t{TX, TY, NT != 0, K};
+        if (!ih::tile_supported(B, t)) continue;
+        if (K && !ih::fused_supported(ih::make_geom(H, W, B, t))) continue;
+        c.best[TuneKey{H, W, B, NB}] = t;
     }
 }
 
@@ -287,22 +307,32 @@ void save_cache(TuneCache& c)
     if (!path) return;
     std::ofstream out(path);
     for (auto& kv : c.best)
-        out << "gfx950 " << kv.first.H << ' ' << kv.first.W << ' ' << kv.first.B << ' ' << kv.first.nb << ' ' << kv.second.TX
-            << ' ' << kv.second.TY << ' ' << (kv.second.nontemporal ? 1 : 0) << '\n';
+        out << kCacheTag << ' ' << kv.first.H << ' ' << kv.first.W << ' ' << kv.first.B << ' ' << kv.first.nb << ' '
+            << kv.second.TX << ' ' << kv.second.TY << ' ' << (kv.second.nontemporal ? 1 : 0) << ' ' << kv.second.K
+            << '\n';
 }
 
-std::vector<ih::TileChoice> candidates(int32_t H, int32_t B)
+// Candidates of a class of H x W frames: every supported tile width, band
+// height and store flavour, each under both carry schedules (reduce-then-scan,
+// and fused with carry bands of ceil(nTY / 16) tile bands).
+std::vector<ih::TileChoice> candidates(int32_t H, int32_t W, int32_t B)
 {
     std::vector<ih::TileChoice> c;
     for (int tx : {32, 64, 128})
         for (int ty : {16, 32, 64, 128, 256})
-            for (bool nt : {false, true}) {
-                ih::TileChoice t{tx, ih::even_band_height(H, ty), nt};
-                if (!ih::tile_supported(B, t)) continue;
-                bool dup = false;
-                for (const ih::TileChoice& u : c) dup |= u.TX == t.TX && u.TY == t.TY && u.nontemporal == t.nontemporal;
-                if (!dup) c.push_back(t);
-            }
+            for (bool nt : {false, true})
+                for (int fused : {0, 1}) {
+                    ih::TileChoice t{tx, ih::even_band_height(H, ty), nt, 0};
+                    if (!ih::tile_supported(B, t)) continue;
+                    if (fused) {
+                        t.K = ih::fused_bands((H + t.TY - 1) / t.TY, 16);
+                        if (!ih::fused_supported(ih::make_geom(H, W, B, t))) continue;
+                    }
+                    bool dup = false;
+                    for (const ih::TileChoice& u : c)
+                        dup |= u.TX == t.TX && u.TY == t.TY && u.nontemporal == t.nontemporal && u.K == t.K;
+                    if (!dup) c.push_back(t);
+                }
     return c;
 }
 
@@ -374,6 +404,7 @@ ih_status time_candidate(const std::vector<ih_frame_desc>& descs, const ih::Tile
     p->tiles.assign(descs.size(), t);
     p->use_graph = false;
     p->group_bytes = -1;
+    p->stream = s;
     ih_status st = build_plan(p);
     hipEvent_t a = nullptr, b = nullptr;
     if (st == IH_OK) {
@@ -396,7 +427,8 @@ ih_status time_candidate(const std::vector<ih_frame_desc>& descs, const ih::Tile
     }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
-    if (p->d_scratch || p->d_image) (void)hipDeviceSynchronize();
+    // everything the candidate ran is on s
+    if (p->d_scratch || p->d_image) (void)hipStreamSynchronize(s);
     free_plan(p);
     return st;
 }
@@ -424,8 +456,8 @@ ih_status autotune(ih_batch_plan* p, hipStream_t s)
             ih::TileChoice best = batch_default_tile(descs, kv.first.B);
             float best_ms = 1e30f;
             if (ih_status st = time_candidate(descs, best, s, &best_ms)) return st;
-            for (const ih::TileChoice& t : candidates(kv.first.H, kv.first.B)) {
-                if (t.TX == best.TX && t.TY == best.TY && t.nontemporal == best.nontemporal) continue;
+            for (const ih::TileChoice& t : candidates(kv.first.H, kv.first.W, kv.first.B)) {
+                if (t.TX == best.TX && t.TY == best.TY && t.nontemporal == best.nontemporal && t.K == best.K) continue;
                 float ms = 0.f;
                 if (ih_status st = time_candidate(descs, t, s, &ms)) return st;
                 if (ms < 0.98f * best_ms) { best_ms = ms; best = t; }
@@ -450,9 +482,10 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     *plan = nullptr;
     if (n == 0 || !frames) return fail(IH_ERR_INVALID_ARG, "need at least one frame");
     if (n > (1u << 20)) return fail(IH_ERR_RANGE, "too many frames (%zu)", n);
-    ih_batch_options o{0, 1, 0, 0, -1, 0};
+    ih_batch_options o{0, 1, 0, 0, -1, 0, -1};
     if (opt) o = *opt;
     const bool forced = o.tile_x > 0 || o.tile_y > 0;
+    if (o.carry_bands < -1) return fail(IH_ERR_INVALID_ARG, "carry_bands=%d must be >= -1", o.carry_bands);
     for (size_t k = 0; k < n; ++k) {
         const ih_frame_desc& d = frames[k];
         if (!d.frame || !d.out) return fail(IH_ERR_INVALID_ARG, "frame %zu: null pointer", k);
@@ -477,6 +510,7 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     }
     ih_batch_plan* p = new ih_batch_plan;
     (void)hipGetDevice(&p->device);
+    p->stream = static_cast<hipStream_t>(stream);
     p->descs.assign(frames, frames + n);
     for (size_t k = 0; k < n; ++k) {
         if (frames[k].lut) {
@@ -515,6 +549,18 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     }
     if (st == IH_OK && o.nontemporal >= 0)
         for (auto& t : p->tiles) t.nontemporal = o.nontemporal != 0;
+    // A forced carry schedule: reduce-then-scan (0), or fused with that many
+    // tile bands per carry band, clamped to each frame's band count and kept
+    // only where the frame's geometry supports it.
+    for (size_t k = 0; st == IH_OK && o.carry_bands >= 0 && k < n; ++k) {
+        ih::TileChoice& t = p->tiles[k];
+        t.K = 0;
+        if (o.carry_bands == 0) continue;
+        const int32_t nTY = (frames[k].H + t.TY - 1) / t.TY;
+        ih::TileChoice f = t;
+        f.K = std::min(o.carry_bands, nTY);
+        if (ih::fused_supported(ih::make_geom(frames[k].H, frames[k].W, frames[k].B, f))) t = f;
+    }
     // Frames with bin tables: the table kernels exist for tiles up to 64 wide
     // (regular stores); the caller's table pointers are not kept.
     for (size_t k = 0; st == IH_OK && k < n; ++k) {
@@ -540,10 +586,26 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     return IH_OK;
 }
 
+ih_status launch_plan(ih_batch_plan* p, hipStream_t s);
+
 ih_status ih_batch_plan_launch(ih_batch_plan* p, ih_stream_t stream)
 {
     if (!p) return fail(IH_ERR_INVALID_ARG, "plan must be non-null");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ih_status st = launch_plan(p, s)) return st;
+    // the plan's last launch, for destroy to wait on
+    if (!p->ev_done) {
+        hipError_t e = hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    hipError_t e = hipEventRecord(p->ev_done, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->launched = true;
+    return IH_OK;
+}
+
+ih_status launch_plan(ih_batch_plan* p, hipStream_t s)
+{
     ih::PhaseTimer timer;
     const bool prof = ih::profiling_on();
     if (!p->groups.empty()) {
@@ -572,9 +634,13 @@ ih_status ih_batch_plan_launch(ih_batch_plan* p, ih_stream_t stream)
 ih_status ih_batch_plan_destroy(ih_batch_plan* p)
 {
     if (!p) return IH_OK;
-    hipError_t e = hipDeviceSynchronize();
+    // wait for the plan's own work only: the last launch (launches of one
+    // plan are ordered, see ih_batch_plan_launch) and the creation stream
+    hipError_t e = p->launched ? hipEventSynchronize(p->ev_done) : hipSuccess;
+    hipError_t e2 = hipStreamSynchronize(p->stream);
     free_plan(p);
-    if (e != hipSuccess) return hip_fail(e, "synchronize before destroy");
+    if (e != hipSuccess) return hip_fail(e, "wait for the plan's last launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "synchronize the creation stream");
     return IH_OK;
 }
 
@@ -595,6 +661,23 @@ ih_status ih_batch_plan_info(const ih_batch_plan* p, ih_batch_info* info)
     for (const PlanGroup& G : p->groups) count(G.image);
     info->kernel_launches = launches;
     info->tile_launches = tile_launches;
+    return IH_OK;
+}
+
+ih_status ih_batch_plan_frame_schedule(const ih_batch_plan* p, size_t k, ih_frame_schedule* sched)
+{
+    if (!p || k >= p->descs.size() || !sched) return fail(IH_ERR_INVALID_ARG, "bad plan, index or output pointer");
+    sched->tile_x = p->tiles[k].TX;
+    sched->tile_y = p->tiles[k].TY;
+    sched->nontemporal = p->tiles[k].nontemporal ? 1 : 0;
+    sched->carry_bands = p->tiles[k].K;
+    int32_t group = 0;
+    for (size_t g = 0, first = 0; g < p->groups.size(); ++g) {
+        const size_t frames_in = p->groups[g].frames;
+        if (k >= first && k < first + frames_in) group = (int32_t)g;
+        first += frames_in;
+    }
+    sched->group = group;
     return IH_OK;
 }
 

@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -55,6 +56,13 @@ ih_status get_scratch(hipStream_t stream, size_t bytes, void** out)
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(IH_ERR_OOM, "hipMalloc(%zu) for scratch failed: %s", want, hipGetErrorString(e));
+    }
+    // the fused schedule's arrival counters start at zero (stream order puts
+    // this before every kernel that uses the buffer)
+    e = hipMemsetAsync(p, 0, std::min(want, (size_t)ih::kCounterWords * sizeof(uint32_t)), stream);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "hipMemsetAsync");
     }
     c.bufs[key] = std::make_pair(p, want);
     *out = p;
@@ -217,6 +225,20 @@ ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, 
     if (e != hipSuccess) return hip_fail(e, "bin table upload");
     return enqueue_frame(frame, out, static_cast<uint32_t*>(scratch), g, t.nontemporal, s,
                          reinterpret_cast<const uint8_t*>(dlut));
+}
+
+ih_status ih_write_reference(uint32_t* out, int32_t H, int32_t W, int32_t B, int32_t tile_x, int32_t tile_y,
+                             ih_stream_t stream)
+{
+    if (!out) return fail(IH_ERR_INVALID_ARG, "out must be non-null");
+    if (ih_status st = ih::check_shape(H, W, B)) return st;
+    if (B > 64) return fail(IH_ERR_INVALID_ARG, "the write reference takes B <= 64 (one bin per lane)");
+    if (tile_x != 32 && tile_x != 64 && tile_x != 128) return fail(IH_ERR_INVALID_ARG, "tile_x must be 32, 64 or 128");
+    if (tile_y < 1) return fail(IH_ERR_INVALID_ARG, "tile_y must be >= 1");
+    if (reinterpret_cast<uintptr_t>(out) & 3u) return fail(IH_ERR_INVALID_ARG, "out must be 4-byte aligned");
+    hipError_t e = ih::launch_write_reference(out, H, W, B, tile_x, tile_y, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return IH_OK;
 }
 
 ih_status ih_query(const ih_view* ih, const ih_rect* rects, size_t n, uint32_t* hists)

@@ -8,10 +8,12 @@ namespace ih {
 ScratchLayout scratch_layout(const Geom& g)
 {
     ScratchLayout s;
-    s.rowc = 0;
+    const size_t bands = g.K ? (size_t)g.nS * g.K : (size_t)g.nTY;
+    s.cnt = 0;
+    s.rowc = kCounterWords;
     s.colc = s.rowc + (size_t)g.H * g.nTX * g.B;
-    s.corner = s.colc + (size_t)g.nTY * g.W * g.B;
-    s.words = s.corner + (size_t)g.nTY * g.nTX * g.B;
+    s.corner = s.colc + bands * g.W * g.B;
+    s.words = s.corner + bands * g.nTX * g.B;
     return s;
 }
 
@@ -19,8 +21,21 @@ FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, con
                      const uint8_t* lut)
 {
     const ScratchLayout sl = scratch_layout(g);
-    return FrameArgs{frame, out, scratch + sl.rowc, scratch + sl.colc, scratch + sl.corner, lut, g};
+    return FrameArgs{frame, out, scratch + sl.rowc, scratch + sl.colc, scratch + sl.corner, scratch + sl.cnt,
+                     lut, g};
 }
+
+bool fused_supported(const Geom& g)
+{
+    return g.K >= 1 && (int64_t)g.nTX + g.nS <= kCounterWords && (int64_t)g.K * g.TY <= 65535;
+}
+
+int32_t fused_bands(int32_t nTY, int32_t max_bands)
+{
+    return (nTY + max_bands - 1) / max_bands;
+}
+
+int64_t count_tile_blocks(const Geom& g) { return (int64_t)g.nTX * (g.K ? g.nS : g.nTY); }
 
 int bins_per_lane(int B) { return B <= 64 ? 1 : (B <= 128 ? 2 : 4); }
 
@@ -35,6 +50,8 @@ Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t)
     g.L = (B + g.BPL - 1) / g.BPL;
     g.S = kWave / g.L;
     g.nJG = (g.nTX + g.S - 1) / g.S;
+    g.K = t.K > 0 ? t.K : 0;
+    g.nS = g.K ? (g.nTY + g.K - 1) / g.K : 0;
     return g;
 }
 

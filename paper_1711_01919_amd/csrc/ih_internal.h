@@ -16,21 +16,45 @@ constexpr int kAggThreads = 256;     // threads per block of the per-tile count 
 // Tile decomposition of one frame.  A tile is TY rows x TX columns.  In the
 // tile pass a wave covers S horizontally adjacent tiles ("segments"); inside a
 // segment, L lanes each own BPL consecutive bins.
+//
+// Carry schedule.  K == 0: reduce-then-scan -- the count launch counts each
+// tile, then two scan launches turn the counts into carries, then the tile
+// pass.  K >= 1: fused -- the count launch counts carry bands of K tile bands
+// (nS of them) and scans the carries itself (the last block to finish a tile
+// column scans that column, the last block to finish a carry band scans that
+// band), so the tile pass follows it directly.
 struct Geom {
     int32_t H, W, B;
     int32_t TX, TY;          // tile width (columns) and height (rows)
     int32_t nTX, nTY;        // tiles across and down
     int32_t BPL, L, S;       // bins per lane, lanes per segment, segments per wave
     int32_t nJG;             // column groups (ceil(nTX / S)) = waves per tile row
+    int32_t K, nS;           // fused schedule: tile bands per carry band, carry bands (0, 0: reduce-then-scan)
 };
 
+// Arrival counters of the fused schedule sit in the first kCounterWords words
+// of every frame's scratch, whatever the schedule, so that no carry of any
+// frame ever lands on them.  They start at zero (cleared when the scratch is
+// allocated) and the last block to arrive resets its counter, so they are
+// zero again after every launch.
+constexpr int32_t kCounterWords = 4096;
+
 // Scratch layout (uint32 words) for one frame:
-//   rowc   [nTX][H][B]    left carries: pixels of row y left of segment j, per bin
-//                         (segment-major, so a tile's rows are one contiguous run)
-//   colc   [nTY][W][B]    column counts per tile band, scanned to top carries
-//   corner [nTY][nTX][B]  per-tile totals, scanned to top-left corner counts
+//   cnt    [kCounterWords]  fused schedule: arrivals per tile column (nTX), then
+//                           per carry band (nS)
+//   rowc   [nTX][H][B]      left carries: pixels of row y left of segment j, per bin
+//                           (segment-major, so a tile's rows are one contiguous run)
+//   reduce-then-scan:
+//   colc   [nTY][W][B]      column counts per tile band, scanned to top carries
+//   corner [nTY][nTX][B]    per-tile totals, scanned to top-left corner counts
+//   fused (carry band I, snapshot s < K):
+//   colc   [nS][K][W][B]    s < K-1: column counts of the band's first s+1 tile
+//                           bands; s = K-1: of the whole band, scanned down the
+//                           bands to top carries
+//   corner [nS][K][nTX][B]  the same for tile-column totals, each snapshot
+//                           scanned across the tile columns
 struct ScratchLayout {
-    size_t rowc, colc, corner, words;
+    size_t cnt, rowc, colc, corner, words;
 };
 ScratchLayout scratch_layout(const Geom& g);
 
@@ -41,6 +65,7 @@ struct FrameArgs {
     uint32_t* rowc;
     uint32_t* colc;
     uint32_t* corner;
+    uint32_t* cnt;
     const uint8_t* lut;      // device bin table (256 entries, non-decreasing, < B); null: floor(v B / 256)
     Geom g;
 };
@@ -58,10 +83,11 @@ struct Job {
     int32_t pad;
 };
 
-// Tile choice (TX, TY, store flavour) for a frame shape.
+// Tile choice (TX, TY, store flavour, carry schedule) for a frame shape.
 struct TileChoice {
     int32_t TX, TY;
     bool nontemporal;
+    int32_t K = 0;           // 0: reduce-then-scan; >= 1: fused with K tile bands per carry band
 };
 
 int bins_per_lane(int B);
@@ -75,6 +101,15 @@ TileChoice binmajor_tile(int32_t H, int32_t W, int32_t B);
 // short work items that leave the device half idle at the end of a launch.
 int32_t even_band_height(int32_t H, int32_t TY);
 bool tile_supported(int32_t B, const TileChoice& t);
+// The fused schedule for this geometry: enough arrival counters, and carry
+// bands whose per-column counts fit 16 bits.
+bool fused_supported(const Geom& g);
+// Carry bands of about `target` tile bands' worth for the fused schedule:
+// the K that leaves at most `max_bands` carry bands.
+int32_t fused_bands(int32_t nTY, int32_t max_bands);
+// Blocks of a frame's count launch: row-carry blocks, then tile (or carry
+// band) blocks.
+int64_t count_tile_blocks(const Geom& g);
 
 // Column groups [0, n) run the unguarded tile kernel; the rest the guarded
 // one.  Unguarded groups hold S whole TX-wide segments, 16-byte aligned.
@@ -139,6 +174,15 @@ hipError_t launch_tile_bm_batch(int bg, const FrameArgs* frames, const Job* jobs
 // Copy a host bin table (256 bytes, passed by value as a kernel argument) to
 // device memory dst (64 uint32, 4-byte aligned), in stream order.
 hipError_t launch_lut_store(const uint8_t* lut_host, uint32_t* dst, hipStream_t stream);
+
+// Write reference: the tile pass's store stream (B <= 64, TX in {32, 64,
+// 128}) without loads or arithmetic.
+hipError_t launch_write_reference(uint32_t* out, int32_t H, int32_t W, int32_t B, int32_t TX, int32_t TY,
+                                  hipStream_t stream);
+
+// Load every kernel's code object now (hipFuncGetAttributes on one kernel of
+// each), so that no request pays for it on a kernel's first launch.
+hipError_t preload_kernels();
 
 // ---- region query ---------------------------------------------------------
 // binmajor: ih holds the b x h x w layout instead of H x W x B.

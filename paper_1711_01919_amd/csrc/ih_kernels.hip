@@ -24,65 +24,14 @@
 // Each phase has one per-frame body.  Single-frame kernels take the frame by
 // value; batched kernels map their blocks (or work items) to frames through a
 // sorted job table and run the same body.
-#include "ih_internal.h"
+#include "ih_device.h"
+#include "ih_tile_fns.h"
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 namespace ih {
-
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Every buffer the kernels touch is device (global) memory.  Pointers read
-// from a device table carry no address space, and accesses through them would
-// compile to flat instructions, which also count against the LDS/scalar
-// counter; casting to the global address space keeps them global_*.
-#define IH_GLOBAL __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ IH_GLOBAL T* gmem(T* p)
-{
-    return (IH_GLOBAL T*)p;
-}
-
-// The frame and job tables of a batched launch are read-only for the whole
-// launch and indexed by wave-uniform values; reading them through the
-// constant address space lets them come in with scalar loads, so everything
-// derived from them (sizes, loop bounds, pointers) stays wave-uniform.
-#define IH_CONST __attribute__((address_space(4)))
-template <class T>
-__device__ __forceinline__ const IH_CONST T* cmem(const T* p)
-{
-    return (const IH_CONST T*)p;
-}
-template <class T>
-__device__ __forceinline__ T cload(const T* table, int64_t idx)
-{
-    T v;
-    __builtin_memcpy(&v, cmem(table) + idx, sizeof(T));
-    return v;
-}
-
-// Index of the calling wave within its workgroup.  The value is the same on
-// every lane of a wave, and saying so keeps what is derived from it (work
-// item, frame, loop bounds) in scalar registers.
-__device__ __forceinline__ int wave_in_block()
-{
-    return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-}
-
-// Largest job whose `begin` is <= idx (jobs sorted by begin, jobs[0].begin == 0).
-// idx is uniform across the caller's wave, so the loads stay scalar.
-__device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs, int64_t idx)
-{
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].begin <= idx) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 // ---------------------------------------------------------------------------
 // Phase 1a: left carries of every row (rowcarry)
@@ -102,30 +51,6 @@ __device__ __forceinline__ void lds_inc8(uint32_t* h, uint32_t e)
 __device__ __forceinline__ uint32_t lds_get8(const uint32_t* h, uint32_t e)
 {
     return (h[e >> 2] >> ((e & 3u) << 3)) & 0xFFu;
-}
-
-// Bin of a pixel value.  A frame either uses the uniform bins floor(v B / 256)
-// or a table of 256 bins (non-decreasing, so each bin is one value range),
-// which the count kernels stage in LDS, four entries per word.
-__device__ __forceinline__ void stage_lut(const FrameArgs& f, uint32_t* lutw, int tid, int nthreads)
-{
-    if (f.lut)
-        for (int e = tid; e < 64; e += nthreads) lutw[e] = reinterpret_cast<const IH_GLOBAL uint32_t*>(gmem(f.lut))[e];
-}
-__device__ __forceinline__ uint32_t bin_of(const FrameArgs& f, const uint32_t* lutw, uint32_t v, uint32_t B)
-{
-    return f.lut ? (lutw[v >> 2] >> (8 * (v & 3u))) & 0xFFu : (v * B) >> 8;
-}
-
-// Entries of a non-decreasing 256-entry bin table below bin b, i.e. the first
-// value of bin b (binary search in nine halving steps).
-__device__ __forceinline__ uint32_t lut_count_below(const IH_GLOBAL uint8_t* lut, uint32_t b)
-{
-    uint32_t pos = 0;
-#pragma unroll 1
-    for (uint32_t step = 256; step > 0; step >>= 1)
-        if (pos + step <= 256 && lut[pos + step - 1] < b) pos += step;
-    return pos;
 }
 
 // The row-carry work is one wave's own: its LDS region is private and it
@@ -234,10 +159,37 @@ __device__ __forceinline__ uint32_t lds_get16(const uint32_t* h, uint32_t e)
     return (h[e >> 1] >> ((e & 1u) << 4)) & 0xFFFFu;
 }
 
+// Pixels of rows [ya, yb) and columns [x0, x0 + tw) added to the per-column
+// bin counters colh (thread tid takes column tid % TX of every
+// (kAggThreads / TX)-th row).
+template <int TX>
+__device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* lutw, uint32_t* colh, int ya, int yb,
+                                           int x0, int tw)
+{
+    constexpr int kRowsPerPass = kAggThreads / TX;
+    const Geom& g = f.g;
+    const int tr = (int)threadIdx.x / TX, tx = (int)threadIdx.x % TX;
+    if (tx >= tw) return;
+    const int th = yb - ya;
+    const IH_GLOBAL uint8_t* p = gmem(f.frame) + (size_t)ya * g.W + x0 + tx;
+    constexpr int U = 8;                       // rows whose pixels are in flight together
+    for (int r0 = tr; r0 < th; r0 += U * kRowsPerPass) {
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = r0 + u * kRowsPerPass;
+            v[u] = r < th ? (uint32_t)p[(size_t)r * g.W] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (r0 + u * kRowsPerPass < th)
+                lds_inc16(colh, (uint32_t)(tx * g.B) + bin_of(f, lutw, v[u], (uint32_t)g.B));
+    }
+}
+
 template <int TX>
 __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint32_t* colh, uint32_t* lutw)
 {
-    constexpr int kRowsPerPass = kAggThreads / TX;
     const Geom& g = f.g;
     const int B = g.B;
     const int i = (int)(tile / g.nTX);
@@ -246,27 +198,11 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     const int tw = min(TX, g.W - x0);
     const int th = min(g.TY, g.H - y0);
     const int tid = threadIdx.x;
-    const int tr = tid / TX, tx = tid % TX;
 
     for (int e = tid; e < (TX * B + 1) / 2; e += kAggThreads) colh[e] = 0;
     stage_lut(f, lutw, tid, kAggThreads);
     __syncthreads();
-    if (tx < tw) {
-        const IH_GLOBAL uint8_t* p = gmem(f.frame) + (size_t)y0 * g.W + x0 + tx;
-        constexpr int U = 8;                       // rows whose pixels are in flight together
-        for (int r0 = tr; r0 < th; r0 += U * kRowsPerPass) {
-            uint32_t v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int r = r0 + u * kRowsPerPass;
-                v[u] = r < th ? (uint32_t)p[(size_t)r * g.W] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (r0 + u * kRowsPerPass < th)
-                    lds_inc16(colh, (uint32_t)(tx * B) + bin_of(f, lutw, v[u], (uint32_t)B));
-        }
-    }
+    count_rows<TX>(f, lutw, colh, y0, y0 + th, x0, tw);
     __syncthreads();
     for (int e = tid; e < tw * B; e += kAggThreads)
         gmem(f.colc)[((size_t)i * g.W + x0) * B + e] = lds_get16(colh, (uint32_t)e);
@@ -277,54 +213,6 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     }
 }
 
-// Phase 1 of a single frame in one launch: blocks [0, row_blocks) hold four
-// row-carry waves each (rows 4 b .. 4 b + 3), the other blocks one tile of
-// column counts each; both kinds run side by side and use the dynamic LDS
-// buffer by role.  The batched form does the same per frame: a job's jg_begin
-// holds its frame's row-block count, followed by the frame's tile blocks.
-constexpr int kRowsPerCountBlock = kAggThreads / kWave;
-
-__host__ __device__ inline size_t agg_lds_bytes(int TX, int B)
-{
-    return ((size_t)TX * B + 1) / 2 * 4 + 256;
-}
-
-template <int TX>
-__global__ __launch_bounds__(kAggThreads)
-void count_kernel(FrameArgs f, int32_t row_blocks)
-{
-    extern __shared__ uint32_t lds[];
-    if ((int32_t)blockIdx.x < row_blocks) {
-        const int w = wave_in_block();
-        const int64_t y = (int64_t)blockIdx.x * kRowsPerCountBlock + w;
-        if (y < f.g.H) rowcarry_body(f, y, lds + (size_t)w * (rowcarry_lds_bytes(f.g) / 4));
-        return;
-    }
-    uint32_t* colh = lds;
-    agg_body<TX>(f, (int64_t)blockIdx.x - row_blocks, colh, colh + ((size_t)TX * f.g.B + 1) / 2);
-}
-
-template <int TX>
-__global__ __launch_bounds__(kAggThreads)
-void count_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
-{
-    extern __shared__ uint32_t lds[];
-    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
-    const FrameArgs f = cload(frames, jb.frame);
-    const int64_t local = (int64_t)blockIdx.x - jb.begin;
-    if (local < jb.jg_begin) {
-        const int w = wave_in_block();
-        const int64_t y = local * kRowsPerCountBlock + w;
-        if (y < f.g.H) rowcarry_body(f, y, lds + (size_t)w * (rowcarry_lds_bytes(f.g) / 4));
-        return;
-    }
-    uint32_t* colh = lds;
-    agg_body<TX>(f, local - jb.jg_begin, colh, colh + ((size_t)TX * f.g.B + 1) / 2);
-}
-
-// ---------------------------------------------------------------------------
-// Phase 2: exclusive scans of the per-tile counts
-// ---------------------------------------------------------------------------
 // Exclusive scan of p[0], p[stride], ... p[(len-1)*stride] in place, starting
 // from `run`.  Loads of a chunk are issued before its stores so that many are
 // in flight at once.
@@ -362,6 +250,201 @@ __device__ __forceinline__ uint32_t sum_seq(const IH_GLOBAL uint32_t* p, int64_t
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// Phase 1, fused schedule: counts and carries of a carry band in one launch
+// ---------------------------------------------------------------------------
+// One 256-thread block per (carry band I, tile column j): the column counts of
+// the band's rows are accumulated tile band by tile band, and after each tile
+// band but the last the block stores a snapshot -- the counts so far of every
+// column and their sum over the tile column -- for the tile band below it.
+// After the last it stores the band's totals.  Then the block reports its
+// arrival on two counters.  The last block of tile column j scans the band
+// totals of its columns down the carry bands (exclusive, in place): top
+// carries at each carry band's first row.  The last block of carry band I
+// scans every snapshot of tile-column totals across the tile columns
+// (exclusive, in place): counts of the band's rows left of each tile column.
+// No block waits for another.  Stores are made visible device-wide before a
+// block reports its arrival, and the last block fences before it reads.
+template <int TX>
+__device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, uint32_t* colh, uint32_t* lutw,
+                                               uint32_t* tot, uint32_t* flag)
+{
+    const Geom& g = f.g;
+    const int B = g.B, K = g.K;
+    const int I = (int)(blk / g.nTX);
+    const int j = (int)(blk - (int64_t)I * g.nTX);
+    const int x0 = j * TX;
+    const int tw = min(TX, g.W - x0);
+    const int Ys = I * K * g.TY;
+    const int Ye = min(g.H, Ys + K * g.TY);
+    const int nk = (Ye - Ys + g.TY - 1) / g.TY;          // tile bands in this carry band
+    const int tid = threadIdx.x;
+    IH_GLOBAL uint32_t* colc = gmem(f.colc);
+    IH_GLOBAL uint32_t* corner = gmem(f.corner);
+
+    for (int e = tid; e < (TX * B + 1) / 2; e += kAggThreads) colh[e] = 0;
+    for (int b = tid; b < B; b += kAggThreads) tot[b] = 0;
+    stage_lut(f, lutw, tid, kAggThreads);
+    __syncthreads();
+    // A carry band of at most kPre passes of rows: every thread loads and bins
+    // all of its pixels of the band at once (one round of loads), then counts
+    // them tile band by tile band.  Taller bands load per tile band.
+    constexpr int kRowsPerPass = kAggThreads / TX;
+    constexpr int kPre = 16;
+    const int tr = tid / TX, tx = tid % TX;
+    const int rows = Ye - Ys;
+    const bool pre = rows <= kPre * kRowsPerPass;           // uniform over the block
+    uint32_t q[kPre];
+    if (pre) {
+        const IH_GLOBAL uint8_t* p = gmem(f.frame) + (size_t)Ys * g.W + x0 + tx;
+        uint32_t v[kPre];
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int r = tr + u * kRowsPerPass;
+            v[u] = (tx < tw && r < rows) ? (uint32_t)p[(size_t)r * g.W] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) q[u] = bin_of(f, lutw, v[u], (uint32_t)B);
+    }
+    for (int k = 0; k < nk; ++k) {
+        const int ya = Ys + k * g.TY;
+        if (pre) {
+            if (tx < tw) {
+#pragma unroll
+                for (int u = 0; u < kPre; ++u) {
+                    const int r = Ys + tr + u * kRowsPerPass;
+                    if (r >= ya && r < min(Ye, ya + g.TY)) lds_inc16(colh, (uint32_t)(tx * B) + q[u]);
+                }
+            }
+        } else {
+            count_rows<TX>(f, lutw, colh, ya, min(Ye, ya + g.TY), x0, tw);
+        }
+        __syncthreads();
+        // snapshot k for tile band k + 1 of the carry band, the totals (K - 1) after the last
+        const int snap = k + 1 < nk ? k : K - 1;
+        const size_t row = (size_t)I * K + snap;
+        IH_GLOBAL uint32_t* cdst = colc + (row * g.W + x0) * B;
+        if ((kAggThreads % B) == 0) {
+            // every element a thread takes is of bin tid % B
+            uint32_t part = 0;
+            for (int e = tid; e < tw * B; e += kAggThreads) {
+                const uint32_t v = lds_get16(colh, (uint32_t)e);
+                cdst[e] = v;
+                part += v;
+            }
+            if (tid < tw * B) atomicAdd(&tot[tid % B], part);
+        } else {
+            for (int e = tid; e < tw * B; e += kAggThreads) {
+                const uint32_t v = lds_get16(colh, (uint32_t)e);
+                cdst[e] = v;
+                atomicAdd(&tot[e % B], v);
+            }
+        }
+        __syncthreads();
+        for (int b = tid; b < B; b += kAggThreads) {
+            corner[(row * g.nTX + j) * B + b] = tot[b];
+            tot[b] = 0;
+        }
+    }
+
+    __threadfence();                                      // this block's stores, device-wide
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t* cnt = f.cnt;
+        const uint32_t a_col = atomicAdd(&cnt[j], 1u);
+        const uint32_t a_band = atomicAdd(&cnt[g.nTX + I], 1u);
+        const uint32_t last_col = a_col == (uint32_t)(g.nS - 1);
+        const uint32_t last_band = a_band == (uint32_t)(g.nTX - 1);
+        // nobody else touches a counter after its last arrival: reset it for the next launch
+        if (last_col) atomicExch(&cnt[j], 0u);
+        if (last_band) atomicExch(&cnt[g.nTX + I], 0u);
+        __threadfence();
+        flag[0] = last_col;
+        flag[1] = last_band;
+    }
+    __syncthreads();
+    const bool last_col = flag[0] != 0, last_band = flag[1] != 0;
+    if (!last_col && !last_band) return;
+    __threadfence();                                      // the other blocks' stores, before reading them
+    if (last_col) {
+        // band totals of columns [x0, x0 + tw): sequences down the carry bands
+        IH_GLOBAL uint32_t* base = colc + ((size_t)(K - 1) * g.W + x0) * B;
+        const int64_t stride = (int64_t)K * g.W * B;
+        for (int e = tid; e < tw * B; e += kAggThreads) scan_seq(base + e, stride, g.nS, 0u);
+    }
+    if (last_band) {
+        // every snapshot row of this carry band, across the tile columns
+        // snapshot rows 0 .. nk-2 and the totals (row K-1): nk rows
+        for (int q = tid; q < nk * B; q += kAggThreads) {
+            const int sidx = q / B, b = q - sidx * B;
+            const int snap = sidx < nk - 1 ? sidx : K - 1;
+            scan_seq(corner + ((size_t)I * K + snap) * g.nTX * B + b, B, g.nTX, 0u);
+        }
+    }
+}
+
+// Phase 1 of a single frame in one launch: blocks [0, row_blocks) hold four
+// row-carry waves each (rows 4 b .. 4 b + 3), the other blocks one tile of
+// column counts each; both kinds run side by side and use the dynamic LDS
+// buffer by role.  The batched form does the same per frame: a job's jg_begin
+// holds its frame's row-block count, followed by the frame's tile blocks.
+constexpr int kRowsPerCountBlock = kAggThreads / kWave;
+
+// LDS of a tile block: 16-bit column counters, the bin table, and for the
+// fused schedule B tile-column totals and two flags.
+__host__ __device__ inline size_t agg_lds_bytes(int TX, int B)
+{
+    return ((size_t)TX * B + 1) / 2 * 4 + 256 + (size_t)B * 4 + 8;
+}
+
+// The tile-block role of the count launch, by schedule.
+template <int TX>
+__device__ __forceinline__ void agg_role(const FrameArgs& f, int64_t blk, uint32_t* lds)
+{
+    uint32_t* colh = lds;
+    uint32_t* lutw = colh + ((size_t)TX * f.g.B + 1) / 2;
+    if (f.g.K) {
+        uint32_t* tot = lutw + 64;
+        agg_fused_body<TX>(f, blk, colh, lutw, tot, tot + f.g.B);
+    } else {
+        agg_body<TX>(f, blk, colh, lutw);
+    }
+}
+
+template <int TX>
+__global__ __launch_bounds__(kAggThreads)
+void count_kernel(FrameArgs f, int32_t row_blocks)
+{
+    extern __shared__ uint32_t lds[];
+    if ((int32_t)blockIdx.x < row_blocks) {
+        const int w = wave_in_block();
+        const int64_t y = (int64_t)blockIdx.x * kRowsPerCountBlock + w;
+        if (y < f.g.H) rowcarry_body(f, y, lds + (size_t)w * (rowcarry_lds_bytes(f.g) / 4));
+        return;
+    }
+    agg_role<TX>(f, (int64_t)blockIdx.x - row_blocks, lds);
+}
+
+template <int TX>
+__global__ __launch_bounds__(kAggThreads)
+void count_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
+{
+    extern __shared__ uint32_t lds[];
+    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
+    const FrameArgs f = cload(frames, jb.frame);
+    const int64_t local = (int64_t)blockIdx.x - jb.begin;
+    if (local < jb.jg_begin) {
+        const int w = wave_in_block();
+        const int64_t y = local * kRowsPerCountBlock + w;
+        if (y < f.g.H) rowcarry_body(f, y, lds + (size_t)w * (rowcarry_lds_bytes(f.g) / 4));
+        return;
+    }
+    agg_role<TX>(f, local - jb.jg_begin, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Phase 2: exclusive scans of the per-tile counts
+// ---------------------------------------------------------------------------
 // Sequences longer than one chunk are split over the four waves of a block:
 // each wave takes a quarter of every sequence of its block's 64, the part
 // totals meet in LDS, and each wave rescans its part from the total of the
@@ -482,300 +565,6 @@ void scan_b_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __rest
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
     scan_b_body<P>(f, (int64_t)blockIdx.x - jb.begin, sums);
-}
-
-// ---------------------------------------------------------------------------
-// Phase 3: the tile pass (hot loop)
-// ---------------------------------------------------------------------------
-template <int BPL, bool NT>
-__device__ __forceinline__ void store_bins(IH_GLOBAL uint32_t* p, const uint32_t (&v)[BPL])
-{
-    if constexpr (BPL == 1) {
-        if constexpr (NT) __builtin_nontemporal_store(v[0], p);
-        else *p = v[0];
-    } else if constexpr (BPL == 2) {
-        u32x2 w = {v[0], v[1]};
-        if constexpr (NT) __builtin_nontemporal_store(w, reinterpret_cast<IH_GLOBAL u32x2*>(p));
-        else *reinterpret_cast<IH_GLOBAL u32x2*>(p) = w;
-    } else {
-        u32x4 w = {v[0], v[1], v[2], v[3]};
-        if constexpr (NT) __builtin_nontemporal_store(w, reinterpret_cast<IH_GLOBAL u32x4*>(p));
-        else *reinterpret_cast<IH_GLOBAL u32x4*>(p) = w;
-    }
-}
-
-// Pixels of row y of a tile segment (TX bytes, packed four per dword).
-template <int TX, bool GUARD, bool UNIFORM>
-__device__ __forceinline__ void load_px(const FrameArgs& f, int y, int x0, int ncols, uint32_t (&px)[TX / 4])
-{
-    const IH_GLOBAL uint8_t* prow = gmem(f.frame) + (size_t)y * f.g.W + x0;
-    if constexpr (!GUARD && UNIFORM) {
-        // One segment per wave: every lane reads the same pixels, so read
-        // them once with scalar loads (their wait never involves the stores).
-        const IH_CONST uint8_t* crow = cmem(f.frame) + (size_t)y * f.g.W + x0;
-#pragma unroll
-        for (int q = 0; q < TX / 16; ++q) {
-            const u32x4 w = *reinterpret_cast<const IH_CONST u32x4*>(crow + 16 * q);
-            px[4 * q + 0] = w.x; px[4 * q + 1] = w.y;
-            px[4 * q + 2] = w.z; px[4 * q + 3] = w.w;
-        }
-    } else if constexpr (!GUARD) {
-#pragma unroll
-        for (int q = 0; q < TX / 16; ++q) {
-            const u32x4 w = *reinterpret_cast<const IH_GLOBAL u32x4*>(prow + 16 * q);
-            px[4 * q + 0] = w.x; px[4 * q + 1] = w.y;
-            px[4 * q + 2] = w.z; px[4 * q + 3] = w.w;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < TX / 4; ++q) px[q] = 0u;
-#pragma unroll
-        for (int k = 0; k < TX; ++k)
-            if (k < ncols) px[k / 4] |= (uint32_t)prow[k] << (8 * (k % 4));
-    }
-}
-
-// Left carries of CH consecutive rows y, y+1, ... of segment j (rows past the
-// band clamped to its last row): CH x B contiguous uint32 in the segment-major
-// rowc, read as one burst.
-template <int BPL, int CH>
-__device__ __forceinline__ void load_carries(const FrameArgs& f, int y, int y_last, int j, int b0, int B,
-                                             const bool (&bvalid)[BPL], uint32_t (&cb)[CH][BPL])
-{
-    const IH_GLOBAL uint32_t* rp = gmem(f.rowc) + (size_t)j * f.g.H * B + b0;
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-        const IH_GLOBAL uint32_t* r = rp + (size_t)min(y + q, y_last) * B;
-#pragma unroll
-        for (int t = 0; t < BPL; ++t) cb[q][t] = bvalid[t] ? r[t] : 0u;
-    }
-}
-
-// One wave, one work item: tile band i (TY rows) x column group jg (S adjacent
-// tile segments).  GUARD=false requires all S segments of the group to exist
-// and be TX columns wide, the frame and W 16-byte aligned, B % BPL == 0 and
-// out aligned to 4*BPL bytes; the host routes everything else to GUARD=true.
-template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE>
-__device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int lane)
-{
-    static_assert(TX % 16 == 0, "pixel rows are loaded 16 bytes at a time");
-    constexpr int LC = BC ? (BC + BPL - 1) / BPL : 1;
-    constexpr bool UNIFORM = BC != 0 && kWave / LC == 1;      // one segment per wave
-    const Geom& g = f.g;
-    const int B = BC ? BC : g.B;
-    const int L = BC ? LC : g.L;
-    const int S = BC ? kWave / LC : g.S;
-
-    const int s = lane / L;
-    const int b0 = (lane - s * L) * BPL;
-    const int j = jg * S + s;
-    if (!((s < S) && (j < g.nTX) && (b0 < B))) return;      // idle lane
-    const int x0 = j * TX;
-    const int ncols = GUARD ? min(TX, g.W - x0) : TX;
-    const int y0 = i * g.TY;
-    const int y1 = min(g.H, y0 + g.TY);
-
-    // Bin b holds the values v in [lo, lo + width).  Uniform bins: v with
-    // ceil(256 b / B) <= v < ceil(256 (b+1) / B), which is floor(v B / 256)
-    // == b.  A bin table: lo = #{v : lut[v] < b}, lo + width = #{v : lut[v]
-    // <= b} (the table never decreases).  A lane tests v - lo < width
-    // (unsigned); an empty bin has width 0.
-    uint32_t lo[BPL], wd[BPL];
-    bool bvalid[BPL];
-#pragma unroll
-    for (int t = 0; t < BPL; ++t) bvalid[t] = GUARD ? b0 + t < B : true;
-    if constexpr (TABLE) {
-        const IH_GLOBAL uint8_t* lt = gmem(f.lut);
-#pragma unroll
-        for (int t = 0; t < BPL; ++t) {
-            const uint32_t l = lut_count_below(lt, (uint32_t)(b0 + t));
-            const uint32_t h = lut_count_below(lt, (uint32_t)(b0 + t + 1));
-            lo[t] = bvalid[t] ? l : 0u;
-            wd[t] = bvalid[t] ? h - l : 0u;
-        }
-    } else {
-#pragma unroll
-        for (int t = 0; t < BPL; ++t) {
-            const int b = b0 + t;
-            const uint32_t l = (uint32_t)(256 * b + B - 1) / (uint32_t)B;
-            const uint32_t h = (uint32_t)(256 * (b + 1) + B - 1) / (uint32_t)B;
-            lo[t] = bvalid[t] ? l : 0u;
-            wd[t] = bvalid[t] ? h - l : 0u;
-        }
-    }
-
-    // Column state: corner + running sum of the top carries along the segment.
-    uint32_t V[BPL][TX];
-    {
-        uint32_t acc[BPL];
-        const IH_GLOBAL uint32_t* cp = gmem(f.corner) + ((size_t)i * g.nTX + j) * B + b0;
-        const IH_GLOBAL uint32_t* tp = gmem(f.colc) + ((size_t)i * g.W + x0) * B + b0;
-#pragma unroll
-        for (int t = 0; t < BPL; ++t) acc[t] = bvalid[t] ? cp[t] : 0u;
-#pragma unroll
-        for (int k = 0; k < TX; ++k) {
-#pragma unroll
-            for (int t = 0; t < BPL; ++t) {
-                if (k < ncols && bvalid[t]) acc[t] += tp[(size_t)k * B + t];
-                V[t][k] = acc[t];
-            }
-        }
-    }
-
-    const bool vec_ok = (b0 + BPL <= B) && (B % BPL == 0) &&
-                        ((reinterpret_cast<uintptr_t>(f.out) & (4 * BPL - 1)) == 0);
-
-    auto row_pass = [&](int y, const uint32_t (&px)[TX / 4], const uint32_t (&c0)[BPL]) {
-        IH_GLOBAL uint32_t* orow = gmem(f.out) + ((size_t)y * g.W + x0) * B + b0;
-        uint32_t cnt[BPL];
-#pragma unroll
-        for (int t = 0; t < BPL; ++t) cnt[t] = c0[t];
-#pragma unroll
-        for (int k = 0; k < TX; ++k) {
-            const uint32_t v = (px[k / 4] >> (8 * (k % 4))) & 0xFFu;
-            uint32_t o[BPL];
-#pragma unroll
-            for (int t = 0; t < BPL; ++t) {
-                cnt[t] += (v - lo[t]) < wd[t] ? 1u : 0u;      // in-lane row scan
-                V[t][k] += cnt[t];                            // column accumulation
-                o[t] = V[t][k];
-            }
-            if constexpr (!GUARD) {
-                store_bins<BPL, NT>(orow + (size_t)k * B, o);
-            } else if (k < ncols) {
-                if (vec_ok) {
-                    store_bins<BPL, NT>(orow + (size_t)k * B, o);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < BPL; ++t)
-                        if (bvalid[t]) orow[(size_t)k * B + t] = o[t];
-                }
-            }
-        }
-    };
-    // Reads beside the write stream cost DRAM time per read burst, so the
-    // left carries come CH rows at a time (one contiguous burst from the
-    // segment-major rowc), loaded a chunk ahead into nb and handed to cb,
-    // which shifts down one row per row.  Pixels of row y+1 are loaded before
-    // the stores of row y (two register sets alternate): loads and stores
-    // share one in-order completion counter on this architecture, so a load
-    // issued after a row's stores could only be waited for behind them.
-    // Rows past the band are clamped, so every wave runs the same control flow.
-    // Several segments per wave (B < 64, compile-time B, whole segments):
-    // the pixels of a chunk of rows for all of the wave's segments come in
-    // one wave-wide load too, and each lane fetches its segment's bytes of a
-    // row from the lane holding them (ds_bpermute).  Piece p (16 bytes) of a
-    // chunk is row r, 16-byte column c, segment s with p = (r * PPR + c) * SC
-    // + s, held by lane p.
-    constexpr int SC = kWave / LC;
-    constexpr int PPR = TX / 16;
-    constexpr bool CHUNK_PX = !GUARD && !UNIFORM && BC != 0 && SC * PPR <= kWave;
-    constexpr int CH = CHUNK_PX ? (8 / BPL < kWave / (SC * PPR) ? 8 / BPL : kWave / (SC * PPR)) : 8 / BPL;
-    uint32_t cb[CH][BPL], nb[CH][BPL];
-    if constexpr (CHUNK_PX) {
-        static_assert(CH * SC * PPR <= kWave, "a pixel chunk must fit one wave-wide load");
-        auto load_chunk_px = [&](int yc, u32x4& dst) {
-            const int p = lane < CH * SC * PPR ? lane : 0;
-            const int ps = p % SC, pc_ = (p / SC) % PPR, pr = p / (SC * PPR);
-            const int row = min(yc + pr, y1 - 1);
-            const int px0 = (jg * SC + ps) * TX + 16 * pc_;
-            dst = *reinterpret_cast<const IH_GLOBAL u32x4*>(gmem(f.frame) + (size_t)row * g.W + px0);
-        };
-        u32x4 pc, pn;
-        load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
-        load_chunk_px(y0, pc);
-        __builtin_amdgcn_s_waitcnt(0);
-        for (int yc = y0; yc < y1; yc += CH) {
-            const bool more = yc + CH < y1;
-            if (more) {
-                load_carries<BPL, CH>(f, yc + CH, y1 - 1, j, b0, B, bvalid, nb);
-                load_chunk_px(yc + CH, pn);
-            }
-#pragma unroll 1
-            for (int r = 0; r < CH; ++r) {
-                const int y = yc + r;
-                uint32_t px[TX / 4];
-#pragma unroll
-                for (int q = 0; q < TX / 4; ++q) {
-                    const int src = (r * PPR + q / 4) * SC + s;
-                    px[q] = (uint32_t)__builtin_amdgcn_ds_bpermute(src * 4, (int)pc[q % 4]);
-                }
-                if (y < y1) row_pass(y, px, cb[0]);
-#pragma unroll
-                for (int q = 0; q + 1 < CH; ++q)
-#pragma unroll
-                    for (int t = 0; t < BPL; ++t) cb[q][t] = cb[q + 1][t];
-            }
-            if (more) {
-#pragma unroll
-                for (int q = 0; q < CH; ++q)
-#pragma unroll
-                    for (int t = 0; t < BPL; ++t) cb[q][t] = nb[q][t];
-                pc = pn;
-            }
-        }
-        return;
-    }
-    uint32_t pxa[TX / 4], pxb[TX / 4];
-    load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
-    load_px<TX, GUARD, UNIFORM>(f, y0, x0, ncols, pxa);
-    // Drain everything once per work item, so that inside the loop the
-    // compiler's counter bookkeeping sees only the in-loop prefetches.
-    __builtin_amdgcn_s_waitcnt(0);
-    for (int yc = y0; yc < y1; yc += CH) {
-        if (yc + CH < y1) load_carries<BPL, CH>(f, yc + CH, y1 - 1, j, b0, B, bvalid, nb);
-#pragma unroll 1
-        for (int r = 0; r < CH; r += 2) {
-            const int y = yc + r;
-            load_px<TX, GUARD, UNIFORM>(f, min(y + 1, y1 - 1), x0, ncols, pxb);
-            __builtin_amdgcn_sched_barrier(0);        // keep the prefetch ahead of the stores
-            if (y < y1) row_pass(y, pxa, cb[0]);
-#pragma unroll
-            for (int q = 0; q + 1 < CH; ++q)
-#pragma unroll
-                for (int t = 0; t < BPL; ++t) cb[q][t] = cb[q + 1][t];
-            load_px<TX, GUARD, UNIFORM>(f, min(y + 2, y1 - 1), x0, ncols, pxa);
-            __builtin_amdgcn_sched_barrier(0);
-            if (y + 1 < y1) row_pass(y + 1, pxb, cb[0]);
-#pragma unroll
-            for (int q = 0; q + 1 < CH; ++q)
-#pragma unroll
-                for (int t = 0; t < BPL; ++t) cb[q][t] = cb[q + 1][t];
-        }
-#pragma unroll
-        for (int q = 0; q < CH; ++q)
-#pragma unroll
-            for (int t = 0; t < BPL; ++t) cb[q][t] = nb[q][t];
-    }
-}
-
-template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE>
-__global__ __launch_bounds__(kWave * kWavesPerBlock)
-void tile_kernel(FrameArgs f, int32_t jg_begin, int32_t jg_count)
-{
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
-    if (item >= (int64_t)f.g.nTY * jg_count) return;      // whole wave leaves together
-    const int i = (int)(item / jg_count);
-    const int jg = jg_begin + (int)(item - (int64_t)i * jg_count);
-    tile_body<BPL, TX, BC, NT, GUARD, TABLE>(f, i, jg, threadIdx.x % kWave);
-}
-
-// Persistent form: each wave strides over the work items of all jobs.
-template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE>
-__global__ __launch_bounds__(kWave * kWavesPerBlock)
-void tile_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs,
-                       int32_t njobs, int64_t nitems)
-{
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block(); item < nitems;
-         item += stride) {
-        const Job jb = cload(jobs, find_job(cmem(jobs), njobs, item));
-        const int64_t local = item - jb.begin;
-        const int i = (int)(local / jb.jg_count);
-        const int jg = jb.jg_begin + (int)(local - (int64_t)i * jb.jg_count);
-        const FrameArgs f = cload(frames, jb.frame);
-        tile_body<BPL, TX, BC, NT, GUARD, TABLE>(f, i, jg, threadIdx.x % kWave);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -961,6 +750,53 @@ void tile_bm_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __res
     tile_bm_body<BG>(f, item - jb.begin);
 }
 
+// ---------------------------------------------------------------------------
+// Write reference: the tile pass's store stream with nothing else
+// ---------------------------------------------------------------------------
+// Same work items, lanes and store order as the tile pass for B <= 64 (one
+// bin per lane, kWave / B segments of TX columns per wave, TY-row bands), but
+// no loads and no arithmetic: each entry gets its row index.  Measures what
+// the device's write path reaches in the tile pass's geometry.
+template <int TX>
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+void write_reference_kernel(uint32_t* out_, int32_t H, int32_t W, int32_t B, int32_t TY, int32_t nJG, int32_t S)
+{
+    IH_GLOBAL uint32_t* out = gmem(out_);
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int nTY = (H + TY - 1) / TY;
+    if (item >= (int64_t)nTY * nJG) return;
+    const int i = (int)(item / nJG), jg = (int)(item - (int64_t)i * nJG);
+    const int lane = threadIdx.x % kWave;
+    const int s = lane / B, b = lane - s * B;
+    const int x0 = (jg * S + s) * TX;
+    if (s >= S || x0 >= W) return;
+    const int ncols = min(TX, W - x0);
+    const int y0 = i * TY, y1 = min(H, y0 + TY);
+    for (int y = y0; y < y1; ++y) {
+        IH_GLOBAL uint32_t* orow = out + ((size_t)y * W + x0) * B + b;
+#pragma unroll
+        for (int k = 0; k < TX; ++k)
+            if (k < ncols) orow[(size_t)k * B] = (uint32_t)y;
+    }
+}
+
+hipError_t launch_write_reference(uint32_t* out, int32_t H, int32_t W, int32_t B, int32_t TX, int32_t TY,
+                                  hipStream_t stream)
+{
+    const int32_t S = kWave / B;
+    const int32_t nTX = (W + TX - 1) / TX, nJG = (nTX + S - 1) / S;
+    const int64_t items = (int64_t)((H + TY - 1) / TY) * nJG;
+    const unsigned blocks = (unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock);
+    const dim3 grid(blocks), block(kWave * kWavesPerBlock);
+    if (TX == 32)
+        hipLaunchKernelGGL(write_reference_kernel<32>, grid, block, 0, stream, out, H, W, B, TY, nJG, S);
+    else if (TX == 64)
+        hipLaunchKernelGGL(write_reference_kernel<64>, grid, block, 0, stream, out, H, W, B, TY, nJG, S);
+    else
+        hipLaunchKernelGGL(write_reference_kernel<128>, grid, block, 0, stream, out, H, W, B, TY, nJG, S);
+    return hipGetLastError();
+}
+
 // A bin table passed by value as a kernel argument, written to device memory.
 struct LutArg {
     uint32_t w[64];
@@ -972,69 +808,39 @@ void lut_store_kernel(LutArg a, uint32_t* dst)
 }
 
 // ---------------------------------------------------------------------------
-// host side: kernel table and launches (geometry and tile choice live in
-// ih_geom.cpp)
+// host side: launches (geometry and tile choice live in ih_geom.cpp, the
+// tile kernels in ih_tile_*.hip)
 // ---------------------------------------------------------------------------
-// Table of compiled tile kernels: single-frame and batched entry per variant.
-struct TileFns {
-    const void* single;
-    const void* batch;
-};
-
-template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE = false>
-static TileFns fns_of()
+hipError_t preload_kernels()
 {
-    return TileFns{reinterpret_cast<const void*>(&tile_kernel<BPL, TX, BC, NT, GUARD, TABLE>),
-                   reinterpret_cast<const void*>(&tile_batch_kernel<BPL, TX, BC, NT, GUARD, TABLE>)};
-}
-
-// Frames binned by a table: runtime B and regular stores only.
-template <bool GUARD>
-static TileFns pick_table(const TileVariant& v)
-{
-    switch (v.bpl) {
-    case 1: return v.tx == 32 ? fns_of<1, 32, 0, false, GUARD, true>() : fns_of<1, 64, 0, false, GUARD, true>();
-    case 2: return v.tx == 32 ? fns_of<2, 32, 0, false, GUARD, true>() : fns_of<2, 64, 0, false, GUARD, true>();
-    default: return fns_of<4, 32, 0, false, GUARD, true>();
+    std::vector<const void*> fns = {
+        reinterpret_cast<const void*>(&count_kernel<32>), reinterpret_cast<const void*>(&count_kernel<64>),
+        reinterpret_cast<const void*>(&count_kernel<128>), reinterpret_cast<const void*>(&count_batch_kernel<32>),
+        reinterpret_cast<const void*>(&count_batch_kernel<64>), reinterpret_cast<const void*>(&count_batch_kernel<128>),
+        reinterpret_cast<const void*>(&scan_a_kernel<1>), reinterpret_cast<const void*>(&scan_a_kernel<kScanParts>),
+        reinterpret_cast<const void*>(&scan_b_kernel<1>), reinterpret_cast<const void*>(&scan_b_kernel<kScanParts>),
+        reinterpret_cast<const void*>(&scan_a_batch_kernel<1>),
+        reinterpret_cast<const void*>(&scan_a_batch_kernel<kScanParts>),
+        reinterpret_cast<const void*>(&scan_b_batch_kernel<1>),
+        reinterpret_cast<const void*>(&scan_b_batch_kernel<kScanParts>),
+        reinterpret_cast<const void*>(&query_kernel<false>), reinterpret_cast<const void*>(&query_kernel<true>),
+        reinterpret_cast<const void*>(&lut_store_kernel)};
+    // one kernel of every tile-pass source (each source is one code object)
+    const TileVariant vs[] = {{1, 64, 64, false, false, false}, {1, 64, 64, false, true, false},
+                              {1, 64, 64, true, false, false}, {1, 64, 64, true, true, false},
+                              {1, 64, 0, false, false, true}};
+    for (const TileVariant& v : vs) {
+        const TileFns f = tile_fns(v);
+        fns.push_back(f.single);
+        fns.push_back(f.batch);
     }
-}
-
-template <int BPL, int TX, bool NT, bool GUARD>
-static TileFns pick_bc(int bc)
-{
-    if constexpr (BPL == 1) {
-        if (bc == 16) return fns_of<1, TX, 16, NT, GUARD>();
-        if (bc == 32) return fns_of<1, TX, 32, NT, GUARD>();
-        if (bc == 64) return fns_of<1, TX, 64, NT, GUARD>();
-        return fns_of<1, TX, 0, NT, GUARD>();
-    } else if constexpr (BPL == 2) {
-        if (bc == 128) return fns_of<2, TX, 128, NT, GUARD>();
-        return fns_of<2, TX, 0, NT, GUARD>();
-    } else {
-        if (bc == 256) return fns_of<4, TX, 256, NT, GUARD>();
-        return fns_of<4, TX, 0, NT, GUARD>();
+    for (const void* fn : fns) {
+        hipFuncAttributes attr;
+        hipError_t e = hipFuncGetAttributes(&attr, fn);
+        if (e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
-
-template <bool NT, bool GUARD>
-static TileFns pick_v(const TileVariant& v)
-{
-    switch (v.bpl) {
-    case 1:
-        if (v.tx == 128) return fns_of<1, 128, 64, NT, GUARD>();      // B == 64 only
-        return v.tx == 32 ? pick_bc<1, 32, NT, GUARD>(v.bc) : pick_bc<1, 64, NT, GUARD>(v.bc);
-    case 2: return v.tx == 32 ? pick_bc<2, 32, NT, GUARD>(v.bc) : pick_bc<2, 64, NT, GUARD>(v.bc);
-    default: return pick_bc<4, 32, NT, GUARD>(v.bc);
-    }
-}
-
-static TileFns tile_fns(const TileVariant& v)
-{
-    if (v.table) return v.guard ? pick_table<true>(v) : pick_table<false>(v);
-    if (v.nt) return v.guard ? pick_v<true, true>(v) : pick_v<true, false>(v);
-    return v.guard ? pick_v<false, true>(v) : pick_v<false, false>(v);
-}
-
 
 int64_t scan_a_blocks(const Geom& g)
 {
@@ -1054,7 +860,7 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
     switch (ph) {
     case Phase::kAgg: {
         const int32_t row_blocks = count_row_blocks(g);
-        const unsigned blocks = (unsigned)row_blocks + (unsigned)g.nTX * (unsigned)g.nTY;
+        const unsigned blocks = (unsigned)row_blocks + (unsigned)count_tile_blocks(g);
         const size_t lds = count_lds(g);
         if (g.TX == 32)
             hipLaunchKernelGGL(count_kernel<32>, dim3(blocks), dim3(kAggThreads), (unsigned)lds, stream, f, row_blocks);
@@ -1065,6 +871,7 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
         break;
     }
     case Phase::kScan:
+        if (g.K) break;                 // fused: the count launch scanned the carries
         if (scan_parts(g.nTY) == 1)
             hipLaunchKernelGGL(scan_a_kernel<1>, dim3((unsigned)scan_a_blocks(g)), dim3(kScanThreads), 0, stream, f);
         else

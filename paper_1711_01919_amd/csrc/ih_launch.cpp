@@ -12,6 +12,12 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t frame_scratch_words(const Geom& g) { return align_up(scratch_layout(g).words, 64); }
 
+size_t batch_image_bound(size_t n)
+{
+    const size_t launches = 3 + 4 + 2 * n + 5;
+    return align_up(n * sizeof(FrameArgs), 256) + launches * 256 + 7 * n * sizeof(Job) + 256;
+}
+
 int phase_of(const BatchLaunch& l)
 {
     switch (l.kind) {
@@ -61,7 +67,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
 
     // Count phase, one launch per tile width: per frame, row-carry blocks of
     // four rows (jg_begin of the job holds their count), then one block per
-    // tile for the column counts.
+    // tile (reduce-then-scan) or per carry band and tile column (fused).
     for (int tx : {32, 64, 128}) {
         std::vector<Job> jobs;
         int64_t begin = 0;
@@ -71,7 +77,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
             if (g.TX != tx) continue;
             const int32_t row_blocks = count_row_blocks(g);
             jobs.push_back(Job{begin, (int32_t)k, row_blocks, 0, 0});
-            begin += row_blocks + (int64_t)g.nTX * g.nTY;
+            begin += row_blocks + count_tile_blocks(g);
             lds = std::max(lds, count_lds(g));
         }
         if (jobs.empty()) continue;
@@ -92,6 +98,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         int64_t begin = 0;
         for (size_t k = 0; k < n; ++k) {
             const Geom& g = frames[k].g;
+            if (g.K) continue;          // fused: carries scanned in the count launch
             if (scan_parts(kind == BatchLaunch::kScanA ? g.nTY : g.nTX) != parts) continue;
             const int64_t nb = kind == BatchLaunch::kScanA ? scan_a_blocks(g) : scan_b_blocks(g);
             if (nb == 0) continue;

@@ -31,6 +31,11 @@ struct BatchImage {
 
 size_t align_up(size_t v, size_t a);
 
+// Bytes of the largest launch image build_batch_image can make for n frames
+// (FrameArgs table, at most one count, four scan and 2 n + 5 tile launches,
+// seven jobs per frame, each table aligned to 256 bytes).
+size_t batch_image_bound(size_t n);
+
 // Scratch words a frame needs for the given tile.
 size_t frame_scratch_words(const Geom& g);
 

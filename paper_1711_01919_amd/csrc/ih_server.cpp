@@ -2,11 +2,15 @@
 // admitted FIFO under an HBM budget, batched continuously onto several HIP
 // streams, with integral histograms kept resident on the device.
 //
-// Threads: callers submit and poll from any thread; one scheduler thread owns
-// every HIP call of the server.  A request moves pending -> admitted
-// (device memory reserved, part of a dispatched batch) -> done (results in
-// pinned host memory) -> collected by ih_poll.
+// Threads: callers submit, poll and query from any thread; one scheduler
+// thread owns every HIP call of the server and all of its device memory.  A
+// request moves pending -> admitted (device memory reserved, part of a
+// dispatched batch) -> done (results in pinned host memory) -> collected by
+// ih_poll.  Queries on a stream's latest resident histogram
+// (ih_server_query_latest) go through the scheduler too, ahead of frame
+// admissions, and their caller waits for them.
 #include "ih.h"
+#include "ih_admission.h"
 #include "ih_internal.h"
 #include "ih_launch.h"
 #include "ih_util.h"
@@ -14,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -39,76 +44,6 @@ uint64_t now_ns()
 }
 
 constexpr size_t kAlign = 256;
-
-// First-fit allocator over one device allocation; offsets only (host-side
-// bookkeeping), neighbours merged on free.  Thread-safe.
-class Arena {
-public:
-    void reset(size_t size)
-    {
-        std::lock_guard<std::mutex> lock(mu_);
-        size_ = size;
-        free_.clear();
-        if (size) free_[0] = size;
-        used_ = 0;
-    }
-    bool alloc(size_t bytes, size_t* off)
-    {
-        std::lock_guard<std::mutex> lock(mu_);
-        bytes = ih::align_up(std::max<size_t>(bytes, 1), kAlign);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            const size_t at = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[at] = rest;
-            used_ += bytes;
-            peak_ = std::max(peak_, used_);
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        std::lock_guard<std::mutex> lock(mu_);
-        bytes = ih::align_up(std::max<size_t>(bytes, 1), kAlign);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const
-    {
-        std::lock_guard<std::mutex> lock(mu_);
-        return used_;
-    }
-    size_t size() const
-    {
-        std::lock_guard<std::mutex> lock(mu_);
-        return size_;
-    }
-    size_t peak() const
-    {
-        std::lock_guard<std::mutex> lock(mu_);
-        return peak_;
-    }
-
-private:
-    mutable std::mutex mu_;
-    size_t size_ = 0, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;
-};
 
 // Pinned host staging: one block allocated on first use and carved by an
 // Arena; requests that do not fit it fall back to recycled size-class buffers.
@@ -178,7 +113,7 @@ private:
     size_t arena_bytes_ = 0;
     bool tried_ = false;
     void* base_ = nullptr;
-    Arena arena_;
+    ih::Arena arena_;
     std::map<size_t, size_t> sizes_;
     std::map<size_t, std::vector<void*>> free_;
 };
@@ -195,18 +130,27 @@ struct Request {
     ih::Geom geom{};
     bool has_lut = false;    // bins from `lut` (copied at submit) instead of Q(v)
     uint8_t lut[256] = {};
+    // a query on the stream's latest resident histogram (ih_server_query_latest)
+    bool latest_query = false;
+    uint64_t frame_ticket = 0;   // the histogram it read
     ih_timing t{0, 0, 0};
     ih_status status = IH_OK;
     std::string detail;      // error text recorded on the scheduler thread
     bool done = false;
 };
 
+// Device and pinned buffers for one batch's launch image (frame table and
+// job tables), two per HIP stream (a stream runs at most two batches).
+struct ImageSlot {
+    void* d = nullptr;
+    void* h = nullptr;
+    bool busy = false;
+};
+
 struct Batch {
     std::vector<std::shared_ptr<Request>> reqs;
-    size_t img_off = 0, img_bytes = 0;
-    void* img_h = nullptr; size_t img_cap = 0;
     hipEvent_t done = nullptr;
-    int stream = 0;
+    int stream = 0, slot = -1;
 };
 
 }  // namespace
@@ -216,30 +160,31 @@ struct ih_server {
     int device = 0;
     // shared state (mu)
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable cv;                            // wakes the scheduler
+    std::condition_variable cv_done;                       // wakes callers waiting for a latest-query
     bool stop = false;
     bool hold = false;                                     // queue requests without admitting them
     uint64_t budget_blocked = 0;                           // admissions deferred for device memory
     uint64_t next_ticket = 1;
     std::deque<std::shared_ptr<Request>> pending;
+    std::deque<std::shared_ptr<Request>> queries;          // latest-queries, served before admissions
     std::unordered_map<uint64_t, std::shared_ptr<Request>> by_ticket;
     size_t admitted = 0;                                   // requests reserved, not yet done
+    int64_t retained = 0;                                  // resident histograms kept (copy for stats)
+    std::map<int32_t, uint64_t> retained_tickets;          // stream -> ticket of its resident histogram (copy)
     // scheduler-thread state
     std::thread worker;
     bool hip_ready = false;
     ih_status hip_status = IH_OK;
     char* d_arena = nullptr;
-    Arena arena;
+    ih::Residency res;                                     // arena + retained histograms
+    size_t image_bytes = 0;                                // one image slot
     std::vector<hipStream_t> streams;
     std::vector<int> inflight_per_stream;
+    std::vector<std::array<ImageSlot, 2>> slots;           // per stream
     std::list<Batch> inflight;
     std::vector<hipEvent_t> event_pool;
     PinnedPool pinned;
-    // retention: latest integral histogram per video stream (LRU order)
-    struct Retained { uint64_t ticket; int32_t H, W, B; size_t off, bytes; };
-    std::map<int32_t, Retained> retained;
-    std::list<int32_t> retained_lru;
-    std::mutex retained_mu;                                // guards retained + its arena blocks for queries
 };
 
 namespace {
@@ -263,19 +208,22 @@ void release_pinned(ih_server* s, Request& r)
     r.frame_h = r.rects_h = r.hists_h = nullptr;
 }
 
-// Scheduler thread: create streams and the arena on first use.
+// Scheduler thread: create streams, image slots and the arena on first use.
 ih_status init_hip(ih_server* s)
 {
     if (s->hip_ready) return s->hip_status;
     s->hip_ready = true;
     hipError_t e = hipSetDevice(s->device);
+    // load every kernel's code now, not on its first launch inside a request
+    if (e == hipSuccess) e = ih::preload_kernels();
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_arena), s->cfg.hbm_budget_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         s->hip_status = hip_fail(e, "server arena");
         return s->hip_status;
     }
-    s->arena.reset(s->cfg.hbm_budget_bytes);
+    s->res.reset(s->cfg.hbm_budget_bytes);
+    s->image_bytes = ih::align_up(ih::batch_image_bound((size_t)s->cfg.max_batch), kAlign);
     for (int k = 0; k < s->cfg.n_hip_streams; ++k) {
         hipStream_t st = nullptr;
         e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -285,6 +233,16 @@ ih_status init_hip(ih_server* s)
         }
         s->streams.push_back(st);
         s->inflight_per_stream.push_back(0);
+        s->slots.emplace_back();
+        for (ImageSlot& sl : s->slots.back()) {
+            e = hipMalloc(&sl.d, s->image_bytes);
+            if (e == hipSuccess) e = hipHostMalloc(&sl.h, s->image_bytes, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                s->hip_status = hip_fail(e, "batch table buffers");
+                return s->hip_status;
+            }
+        }
     }
     return IH_OK;
 }
@@ -301,223 +259,325 @@ hipEvent_t get_event(ih_server* s)
     return e;
 }
 
-// Free the least recently retained histograms until `bytes` more fit (or
-// nothing is left to evict).  Scheduler thread.
-void evict_for(ih_server* s, size_t bytes)
+// Device addresses inside a request's work block: frame, rectangles,
+// results, carries, bin table.
+struct WorkPtrs {
+    uint8_t* frame;
+    ih_rect* rects;
+    uint32_t* hists;
+    uint32_t* scratch;
+    uint32_t* lut;
+};
+WorkPtrs work_ptrs(ih_server* s, const Request& r)
 {
-    std::lock_guard<std::mutex> lock(s->retained_mu);
-    while (!s->retained_lru.empty() && s->arena.size() - s->arena.used() < bytes) {
-        const int32_t sid = s->retained_lru.front();
-        s->retained_lru.pop_front();
-        auto it = s->retained.find(sid);
-        if (it != s->retained.end()) {
-            s->arena.release(it->second.off, it->second.bytes);
-            s->retained.erase(it);
-        }
-    }
+    WorkPtrs w;
+    char* p = s->d_arena + r.work_off;
+    w.frame = reinterpret_cast<uint8_t*>(p);
+    p += r.latest_query ? 0 : ih::align_up((size_t)r.H * r.W, kAlign);     // a query uploads no frame
+    w.rects = reinterpret_cast<ih_rect*>(p);
+    p += ih::align_up(r.nq * sizeof(ih_rect), kAlign);
+    w.hists = reinterpret_cast<uint32_t*>(p);
+    p += ih::align_up(r.nq * r.B * 4, kAlign);
+    w.scratch = reinterpret_cast<uint32_t*>(p);
+    p += r.latest_query ? 0 : ih::align_up(ih::frame_scratch_words(r.geom) * 4, kAlign);
+    w.lut = reinterpret_cast<uint32_t*>(p);
+    return w;
 }
 
-bool reserve(ih_server* s, Request& r)
+// Enqueue one batch of frame requests on its stream: uploads, the three
+// phases for every frame (one launch per phase for all of them, from the
+// batch's image slot), the queries, the result downloads.
+hipError_t enqueue_frames(ih_server* s, Batch& bt, hipStream_t st)
 {
-    const size_t need = ih::align_up(r.ih_bytes, kAlign) + ih::align_up(r.work_bytes, kAlign);
-    if (s->arena.size() - s->arena.used() < need) evict_for(s, need);
-    size_t a = 0, b = 0;
-    if (!s->arena.alloc(r.ih_bytes, &a)) {
-        evict_for(s, s->arena.size());       // fragmentation: drop every retained histogram
-        if (!s->arena.alloc(r.ih_bytes, &a)) return false;
-    }
-    if (!s->arena.alloc(r.work_bytes, &b)) {
-        s->arena.release(a, r.ih_bytes);
-        return false;
-    }
-    r.ih_off = a;
-    r.work_off = b;
-    return true;
-}
-
-// Enqueue one batch on stream k: uploads, the three phases for every frame,
-// the queries, the result downloads, and a completion event.
-ih_status dispatch(ih_server* s, Batch& bt)
-{
-    hipStream_t st = s->streams[bt.stream];
     std::vector<ih::FrameArgs> frames;
     std::vector<char> nt;
+    hipError_t e = hipSuccess;
     for (auto& rp : bt.reqs) {
         Request& r = *rp;
-        char* work = s->d_arena + r.work_off;
-        uint8_t* d_frame = reinterpret_cast<uint8_t*>(work);
-        ih_rect* d_rects = reinterpret_cast<ih_rect*>(work + ih::align_up((size_t)r.H * r.W, kAlign));
-        uint32_t* d_hists = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_rects) +
-                                                        ih::align_up(r.nq * sizeof(ih_rect), kAlign));
-        uint32_t* d_scratch = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_hists) +
-                                                          ih::align_up(r.nq * r.B * 4, kAlign));
+        const WorkPtrs w = work_ptrs(s, r);
         uint32_t* d_out = reinterpret_cast<uint32_t*>(s->d_arena + r.ih_off);
-        uint32_t* d_lut = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_scratch) +
-                                                      ih::align_up(ih::frame_scratch_words(r.geom) * 4, kAlign));
-        hipError_t e = hipMemcpyAsync(d_frame, r.frame_h, (size_t)r.H * r.W, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(w.frame, r.frame_h, (size_t)r.H * r.W, hipMemcpyHostToDevice, st);
         if (e == hipSuccess && r.nq)
-            e = hipMemcpyAsync(d_rects, r.rects_h, r.nq * sizeof(ih_rect), hipMemcpyHostToDevice, st);
-        if (e == hipSuccess && r.has_lut) e = ih::launch_lut_store(r.lut, d_lut, st);
-        if (e != hipSuccess) return hip_fail(e, "request upload");
-        frames.push_back(ih::frame_args(d_frame, d_out, d_scratch, r.geom,
-                                        r.has_lut ? reinterpret_cast<const uint8_t*>(d_lut) : nullptr));
+            e = hipMemcpyAsync(w.rects, r.rects_h, r.nq * sizeof(ih_rect), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && r.has_lut) e = ih::launch_lut_store(r.lut, w.lut, st);
+        if (e == hipSuccess && r.geom.K)             // fused schedule: arrival counters start at zero
+            e = hipMemsetAsync(w.scratch, 0, (size_t)ih::kCounterWords * sizeof(uint32_t), st);
+        if (e != hipSuccess) return e;
+        frames.push_back(ih::frame_args(w.frame, d_out, w.scratch, r.geom,
+                                        r.has_lut ? reinterpret_cast<const uint8_t*>(w.lut) : nullptr));
         nt.push_back(0);
     }
     ih::BatchImage img;
     ih::build_batch_image(frames, nt, &img);
-    bt.img_bytes = img.bytes();
-    if (!s->arena.alloc(bt.img_bytes, &bt.img_off)) return fail(IH_ERR_OOM, "batch tables do not fit the budget");
-    bt.img_h = s->pinned.get(bt.img_bytes, &bt.img_cap);
-    if (!bt.img_h) return fail(IH_ERR_OOM, "pinned staging");
-    std::memcpy(bt.img_h, img.host.data(), bt.img_bytes);
-    void* d_img = s->d_arena + bt.img_off;
-    hipError_t e = hipMemcpyAsync(d_img, bt.img_h, bt.img_bytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = ih::enqueue_batch(img, d_img, -1, st);
+    if (img.bytes() > s->image_bytes) return hipErrorInvalidValue;     // cannot happen: the slot holds the bound
+    ImageSlot& slot = s->slots[bt.stream][bt.slot];
+    std::memcpy(slot.h, img.host.data(), img.bytes());
+    e = hipMemcpyAsync(slot.d, slot.h, img.bytes(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = ih::enqueue_batch(img, slot.d, -1, st);
     for (size_t k = 0; e == hipSuccess && k < bt.reqs.size(); ++k) {
         Request& r = *bt.reqs[k];
         if (!r.nq) continue;
-        const ih::FrameArgs& f = frames[k];
-        const char* work = s->d_arena + r.work_off;
-        const int32_t* d_rects = reinterpret_cast<const int32_t*>(work + ih::align_up((size_t)r.H * r.W, kAlign));
-        uint32_t* d_hists = reinterpret_cast<uint32_t*>(const_cast<char*>(work) + ih::align_up((size_t)r.H * r.W, kAlign) +
-                                                        ih::align_up(r.nq * sizeof(ih_rect), kAlign));
-        e = ih::launch_query(f.out, r.H, r.W, r.B, d_rects, (int64_t)r.nq, d_hists, nullptr, false, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(r.hists_h, d_hists, r.nq * r.B * 4, hipMemcpyDeviceToHost, st);
+        const WorkPtrs w = work_ptrs(s, r);
+        e = ih::launch_query(frames[k].out, r.H, r.W, r.B, reinterpret_cast<const int32_t*>(w.rects), (int64_t)r.nq,
+                             w.hists, nullptr, false, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(r.hists_h, w.hists, r.nq * r.B * 4, hipMemcpyDeviceToHost, st);
     }
-    if (e != hipSuccess) return hip_fail(e, "batch enqueue");
-    bt.done = get_event(s);
-    if (!bt.done) return fail(IH_ERR_HIP, "hipEventCreate failed");
-    e = hipEventRecord(bt.done, st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    return IH_OK;
+    return e;
+}
+
+// Enqueue a query on a resident histogram (a batch of one latest-query).
+hipError_t enqueue_latest_query(ih_server* s, Batch& bt, hipStream_t st)
+{
+    Request& r = *bt.reqs[0];
+    const WorkPtrs w = work_ptrs(s, r);
+    // the scheduler marked the histogram as being read when it admitted the query
+    const uint32_t* ihp = reinterpret_cast<const uint32_t*>(s->d_arena + r.ih_off);
+    hipError_t e = hipMemcpyAsync(w.rects, r.rects_h, r.nq * sizeof(ih_rect), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = ih::launch_query(ihp, r.H, r.W, r.B, reinterpret_cast<const int32_t*>(w.rects), (int64_t)r.nq, w.hists,
+                             nullptr, false, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(r.hists_h, w.hists, r.nq * r.B * 4, hipMemcpyDeviceToHost, st);
+    return e;
+}
+
+// Release what an admitted request holds and mark it finished (caller holds
+// s->mu).  keep_ih: its histogram became its stream's latest instead.
+void finish_locked(ih_server* s, Request& r, ih_status st, const char* detail, bool keep_ih, uint64_t t)
+{
+    s->res.release(r.work_off, r.work_bytes);
+    if (r.latest_query) s->res.release_reader(r.stream_id, r.frame_ticket);
+    else if (!keep_ih) s->res.release(r.ih_off, r.ih_bytes);
+    r.t.t_done_ns = t;
+    r.status = st;
+    if (st != IH_OK) r.detail = detail ? detail : "";
+    r.done = true;
+    if (!r.latest_query) s->admitted -= 1;
+}
+
+// Enqueue one batch on its stream and record its completion event.  The
+// HIP calls run with s->mu released (they touch only the batch's requests,
+// fixed since admission, and scheduler-thread state); the stream and slot are
+// marked busy first.  On a failure after work was enqueued, the stream is
+// drained before the batch's memory goes back.  Caller holds `lock` on s->mu.
+void dispatch(ih_server* s, Batch bt, std::unique_lock<std::mutex>& lock)
+{
+    hipStream_t st = s->streams[bt.stream];
+    const bool query = bt.reqs[0]->latest_query;
+    s->slots[bt.stream][bt.slot].busy = true;
+    s->inflight_per_stream[bt.stream] += 1;
+    lock.unlock();
+    hipError_t e = query ? enqueue_latest_query(s, bt, st) : enqueue_frames(s, bt, st);
+    if (e == hipSuccess) {
+        bt.done = get_event(s);
+        if (!bt.done) e = hipErrorOutOfMemory;
+    }
+    if (e == hipSuccess) e = hipEventRecord(bt.done, st);
+    if (e != hipSuccess) (void)hipStreamSynchronize(st);    // whatever was enqueued has finished
+    lock.lock();
+    if (e == hipSuccess) {
+        s->inflight.push_back(std::move(bt));
+        return;
+    }
+    s->slots[bt.stream][bt.slot].busy = false;
+    s->inflight_per_stream[bt.stream] -= 1;
+    const ih_status fs = hip_fail(e, "batch enqueue");
+    const std::string detail = ih_last_error();
+    (void)hipGetLastError();
+    if (bt.done) s->event_pool.push_back(bt.done);
+    const uint64_t t = now_ns();
+    for (auto& rp : bt.reqs) finish_locked(s, *rp, fs, detail.c_str(), false, t);
+    s->cv_done.notify_all();
+}
+
+// Copies of the retention state that other threads read under s->mu.
+void refresh_residency_locked(ih_server* s)
+{
+    s->retained = (int64_t)s->res.retained_count();
+    s->retained_tickets = s->res.tickets();
 }
 
 // Complete finished batches: stamp, release device memory (keeping the latest
-// histogram of each stream when retention is on).  Returns true if any finished.
-bool reap(ih_server* s)
+// histogram of each stream when retention is on).  Returns true if any
+// finished.  Caller holds s->mu.
+bool reap_locked(ih_server* s)
 {
     bool any = false;
     for (auto it = s->inflight.begin(); it != s->inflight.end();) {
         hipError_t q = hipEventQuery(it->done);
         if (q == hipErrorNotReady) { ++it; continue; }
         const ih_status st = q == hipSuccess ? IH_OK : hip_fail(q, "batch execution");
+        const std::string detail = st == IH_OK ? std::string() : std::string(ih_last_error());
         const uint64_t t = now_ns();
-        s->arena.release(it->img_off, it->img_bytes);
-        s->pinned.put(it->img_h, it->img_cap);
         s->event_pool.push_back(it->done);
+        s->slots[it->stream][it->slot].busy = false;
         s->inflight_per_stream[it->stream] -= 1;
-        {
-            std::lock_guard<std::mutex> lock(s->mu);
-            for (auto& rp : it->reqs) {
-                Request& r = *rp;
-                s->arena.release(r.work_off, r.work_bytes);
-                bool keep = false;
-                if (s->cfg.retain && st == IH_OK) {
-                    std::lock_guard<std::mutex> rl(s->retained_mu);
-                    auto old = s->retained.find(r.stream_id);
-                    if (old != s->retained.end()) {
-                        s->arena.release(old->second.off, old->second.bytes);
-                        s->retained_lru.remove(r.stream_id);
-                    }
-                    s->retained[r.stream_id] = ih_server::Retained{r.ticket, r.H, r.W, r.B, r.ih_off, r.ih_bytes};
-                    s->retained_lru.push_back(r.stream_id);
-                    keep = true;
-                }
-                if (!keep) s->arena.release(r.ih_off, r.ih_bytes);
-                r.t.t_done_ns = t;
-                r.status = st;
-                if (st != IH_OK) r.detail = ih_last_error();
-                r.done = true;
-                s->admitted -= 1;
-            }
+        for (auto& rp : it->reqs) {
+            Request& r = *rp;
+            const bool keep = s->cfg.retain && st == IH_OK && !r.latest_query;
+            if (keep) s->res.retain(r.stream_id, ih::Retained{r.ticket, r.H, r.W, r.B, r.ih_off, r.ih_bytes, 0});
+            finish_locked(s, r, st, detail.c_str(), keep, t);
         }
+        refresh_residency_locked(s);
         it = s->inflight.erase(it);
         any = true;
     }
+    if (any) s->cv_done.notify_all();
     return any;
 }
 
-}  // namespace
-
-namespace {
-
-void fail_pending(ih_server* s, ih_status st)
+// A stream with room for one more batch, and its free image slot.
+bool free_stream(ih_server* s, int* stream, int* slot)
 {
-    // caller holds s->mu
-    const uint64_t t = now_ns();
-    for (auto& rp : s->pending) {
-        rp->status = st;
-        rp->detail = ih_last_error();
-        rp->done = true;
-        rp->t.t_done_ns = t;
+    for (size_t k = 0; k < s->streams.size(); ++k) {
+        if (s->inflight_per_stream[k] >= 2) continue;
+        for (int j = 0; j < 2; ++j)
+            if (!s->slots[k][j].busy) {
+                *stream = (int)k;
+                *slot = j;
+                return true;
+            }
     }
+    return false;
+}
+
+void fail_request_locked(ih_server* s, Request& r, ih_status st, const char* detail)
+{
+    r.status = st;
+    r.detail = detail;
+    r.done = true;
+    r.t.t_done_ns = now_ns();
+    (void)s;
+}
+
+void fail_pending_locked(ih_server* s, ih_status st)
+{
+    const std::string detail = ih_last_error();
+    for (auto& rp : s->pending) fail_request_locked(s, *rp, st, detail.c_str());
+    for (auto& rp : s->queries) fail_request_locked(s, *rp, st, detail.c_str());
     s->pending.clear();
+    s->queries.clear();
+    s->cv_done.notify_all();
+}
+
+// Latest-queries first: each takes a stream and reads its stream's resident
+// histogram (marked as being read until it finishes).
+bool serve_queries_locked(ih_server* s, std::unique_lock<std::mutex>& lock)
+{
+    bool progressed = false;
+    while (!s->queries.empty()) {
+        int k = 0, slot = 0;
+        if (!free_stream(s, &k, &slot)) break;
+        std::shared_ptr<Request> r = s->queries.front();
+        ih::Retained h;
+        if (!s->res.acquire(r->stream_id, &h)) {
+            s->queries.pop_front();
+            fail_request_locked(s, *r, fail(IH_ERR_INVALID_ARG, "stream %d has no resident integral histogram",
+                                            r->stream_id), ih_last_error());
+            s->cv_done.notify_all();
+            progressed = true;
+            continue;
+        }
+        bool bad = false;
+        for (size_t q = 0; q < r->nq && !bad; ++q) {
+            const ih_rect& x = static_cast<const ih_rect*>(r->rects_h)[q];
+            bad = x.x0 < 0 || x.x0 > x.x1 || x.x1 >= h.W || x.y0 < 0 || x.y0 > x.y1 || x.y1 >= h.H;
+        }
+        const size_t hb = ih::align_up(r->nq * (size_t)h.B * 4, kAlign);
+        if (bad) {
+            s->res.release_reader(r->stream_id, h.ticket);
+            s->queries.pop_front();
+            fail_request_locked(s, *r, fail(IH_ERR_INVALID_ARG, "a rectangle is outside the %dx%d frame", h.W, h.H),
+                                ih_last_error());
+            s->cv_done.notify_all();
+            progressed = true;
+            continue;
+        }
+        r->H = h.H; r->W = h.W; r->B = h.B;
+        r->ih_off = h.off;
+        r->frame_ticket = h.ticket;
+        r->work_bytes = ih::align_up(r->nq * sizeof(ih_rect), kAlign) + hb + kAlign;
+        size_t off = 0;
+        const ih::Admit a = s->res.reserve_one(r->work_bytes, !s->inflight.empty(), r->stream_id, &off);
+        if (a == ih::Admit::kWait) {
+            s->res.release_reader(r->stream_id, h.ticket);
+            s->budget_blocked += 1;
+            break;
+        }
+        s->queries.pop_front();
+        if (a == ih::Admit::kNever) {
+            s->res.release_reader(r->stream_id, h.ticket);
+            fail_request_locked(s, *r, fail(IH_ERR_BUDGET, "query results do not fit the budget"), ih_last_error());
+            s->cv_done.notify_all();
+            progressed = true;
+            continue;
+        }
+        r->work_off = off;
+        r->t.t_admit_ns = now_ns();
+        Batch bt;
+        bt.stream = k;
+        bt.slot = slot;
+        bt.reqs.push_back(r);
+        dispatch(s, std::move(bt), lock);
+        progressed = true;
+    }
+    return progressed;
 }
 
 void scheduler(ih_server* s)
 {
+    std::unique_lock<std::mutex> lock(s->mu);
     for (;;) {
         bool progressed = false;
-        if (!s->inflight.empty()) progressed |= reap(s);
-
-        std::unique_lock<std::mutex> lock(s->mu);
+        if (!s->inflight.empty()) progressed |= reap_locked(s);
         if (s->stop && s->inflight.empty()) {
-            fail_pending(s, IH_ERR_SHUTDOWN);
+            fail_pending_locked(s, fail(IH_ERR_SHUTDOWN, "server is shutting down"));
             return;
         }
-        if (!s->stop && !s->hold && !s->pending.empty()) {
-            lock.unlock();
+        if (!s->stop && (!s->queries.empty() || (!s->hold && !s->pending.empty()))) {
             const ih_status hs = init_hip(s);
-            lock.lock();
             if (hs != IH_OK) {
-                fail_pending(s, hs);
+                fail_pending_locked(s, hs);
                 continue;
             }
+            progressed |= serve_queries_locked(s, lock);
+            refresh_residency_locked(s);
+        }
+        if (!s->stop && !s->hold && !s->pending.empty() && s->hip_status == IH_OK) {
             // Continuous batching: every stream with room takes the requests at
             // the head of the queue that fit (FIFO, no overtaking).
-            for (size_t k = 0; k < s->streams.size() && !s->pending.empty(); ++k) {
-                if (s->inflight_per_stream[k] >= 2) continue;
+            int k = 0, slot = 0;
+            while (!s->pending.empty() && free_stream(s, &k, &slot)) {
                 Batch bt;
-                bt.stream = (int)k;
+                bt.stream = k;
+                bt.slot = slot;
                 while (!s->pending.empty() && (int)bt.reqs.size() < s->cfg.max_batch &&
                        (int)s->admitted < s->cfg.max_slots) {
                     std::shared_ptr<Request> r = s->pending.front();
-                    if (!reserve(s, *r)) {
+                    const bool held = !s->inflight.empty() || !bt.reqs.empty();
+                    const ih::Admit a = s->res.reserve(r->ih_bytes, r->work_bytes, held, &r->ih_off, &r->work_off);
+                    if (a == ih::Admit::kWait) {
                         s->budget_blocked += 1;
                         break;
                     }
                     s->pending.pop_front();
+                    if (a == ih::Admit::kNever) {
+                        fail_request_locked(s, *r, fail(IH_ERR_BUDGET, "request does not fit the budget's arena"),
+                                            ih_last_error());
+                        progressed = true;
+                        continue;
+                    }
                     r->t.t_admit_ns = now_ns();
                     s->admitted += 1;
                     bt.reqs.push_back(r);
                 }
+                refresh_residency_locked(s);
                 if (bt.reqs.empty()) break;
-                lock.unlock();
-                ih_status st = dispatch(s, bt);
-                lock.lock();
-                s->inflight_per_stream[k] += 1;
-                if (st != IH_OK && !bt.done) {
-                    // nothing recorded: finish the batch here with the error
-                    for (auto& rp : bt.reqs) {
-                        s->arena.release(rp->work_off, rp->work_bytes);
-                        s->arena.release(rp->ih_off, rp->ih_bytes);
-                        rp->status = st;
-                        rp->detail = ih_last_error();
-                        rp->done = true;
-                        rp->t.t_done_ns = now_ns();
-                        s->admitted -= 1;
-                    }
-                    if (bt.img_bytes && bt.img_h) s->pinned.put(bt.img_h, bt.img_cap);
-                    s->inflight_per_stream[k] -= 1;
-                } else {
-                    s->inflight.push_back(std::move(bt));
-                }
+                dispatch(s, std::move(bt), lock);
                 progressed = true;
             }
         }
         if (!progressed) {
-            // Wake on submit/shutdown, or poll the device again shortly.
+            // Wake on submit/query/shutdown, or poll the device again shortly.
             s->cv.wait_for(lock, std::chrono::microseconds(s->inflight.empty() ? 2000 : 20));
         }
     }
@@ -643,35 +703,50 @@ ih_status ih_server_query_latest(ih_server* s, int32_t stream_id, const ih_rect*
                                  uint32_t* hists_host, uint64_t* frame_ticket)
 {
     if (!s || (nq && (!rects_host || !hists_host))) return fail(IH_ERR_INVALID_ARG, "bad arguments");
-    std::lock_guard<std::mutex> rl(s->retained_mu);
-    auto it = s->retained.find(stream_id);
-    if (it == s->retained.end()) return fail(IH_ERR_INVALID_ARG, "stream %d has no resident integral histogram", stream_id);
-    const ih_server::Retained& k = it->second;
-    if (frame_ticket) *frame_ticket = k.ticket;
-    if (nq == 0) return IH_OK;
-    ih_view v{reinterpret_cast<const uint32_t*>(s->d_arena + k.off), k.H, k.W, k.B, nullptr};
-    uint32_t* d_hists = nullptr;
-    hipError_t e = hipMalloc(&d_hists, nq * k.B * 4);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(IH_ERR_OOM, "query output");
+    if (nq > ((size_t)1 << 24)) return fail(IH_ERR_RANGE, "too many rectangles (%zu)", nq);
+    auto r = std::make_shared<Request>();
+    r->latest_query = true;
+    r->stream_id = stream_id;
+    r->nq = nq;
+    r->t.t_submit_ns = now_ns();
+    if (nq) {
+        // results are at most 256 bins per rectangle; the scheduler checks the
+        // rectangles against the resident histogram's shape
+        r->rects_h = s->pinned.get(nq * sizeof(ih_rect), &r->rects_cap);
+        r->hists_h = s->pinned.get(nq * 256 * 4, &r->hists_cap);
+        if (!r->rects_h || !r->hists_h) {
+            release_pinned(s, *r);
+            return fail(IH_ERR_OOM, "pinned host staging");
+        }
+        std::memcpy(r->rects_h, rects_host, nq * sizeof(ih_rect));
     }
-    hipStream_t st = nullptr;
-    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        (void)hipFree(d_hists);
-        return hip_fail(e, "hipStreamCreate");
+    std::unique_lock<std::mutex> lock(s->mu);
+    if (s->stop) {
+        lock.unlock();
+        release_pinned(s, *r);
+        return fail(IH_ERR_SHUTDOWN, "server is shutting down");
     }
-    v.stream = st;
-    ih_status r = ih_query(&v, rects_host, nq, d_hists);
-    if (r == IH_OK) {
-        e = hipMemcpyAsync(hists_host, d_hists, nq * k.B * 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) r = hip_fail(e, "query download");
+    if (nq == 0) {
+        // nothing to compute: the ticket of the resident histogram, if any
+        const bool any = s->retained_tickets.count(stream_id) != 0;
+        const uint64_t tk = any ? s->retained_tickets[stream_id] : 0;
+        lock.unlock();
+        if (!any) return fail(IH_ERR_INVALID_ARG, "stream %d has no resident integral histogram", stream_id);
+        if (frame_ticket) *frame_ticket = tk;
+        return IH_OK;
     }
-    (void)hipStreamDestroy(st);
-    (void)hipFree(d_hists);
-    return r;
+    s->queries.push_back(r);
+    s->cv.notify_one();
+    s->cv_done.wait(lock, [&] { return r->done; });
+    lock.unlock();
+    const ih_status st = r->status;
+    if (st == IH_OK) {
+        std::memcpy(hists_host, r->hists_h, nq * (size_t)r->B * 4);
+        if (frame_ticket) *frame_ticket = r->frame_ticket;
+    }
+    release_pinned(s, *r);
+    if (st != IH_OK) return fail(st, "%s", r->detail.c_str());
+    return IH_OK;
 }
 
 ih_status ih_server_stats(ih_server* s, ih_server_counters* c)
@@ -680,13 +755,10 @@ ih_status ih_server_stats(ih_server* s, ih_server_counters* c)
     std::lock_guard<std::mutex> lock(s->mu);
     c->pending = (int64_t)s->pending.size();
     c->admitted = (int64_t)s->admitted;
-    c->device_bytes_used = (uint64_t)s->arena.used();
-    c->device_bytes_peak = (uint64_t)s->arena.peak();
+    c->retained = s->retained;
+    c->device_bytes_used = (uint64_t)s->res.arena().used();
+    c->device_bytes_peak = (uint64_t)s->res.arena().peak();
     c->budget_blocked = s->budget_blocked;
-    {
-        std::lock_guard<std::mutex> rl(s->retained_mu);
-        c->retained = (int64_t)s->retained.size();
-    }
     return IH_OK;
 }
 
@@ -712,6 +784,11 @@ ih_status ih_server_destroy(ih_server* s)
     if (s->worker.joinable()) s->worker.join();
     // every batch has completed; release device and host resources
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+    for (auto& pair : s->slots)
+        for (ImageSlot& sl : pair) {
+            if (sl.d) (void)hipFree(sl.d);
+            if (sl.h) (void)hipHostFree(sl.h);
+        }
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->d_arena) (void)hipFree(s->d_arena);
     for (auto& kv : s->by_ticket) release_pinned(s, *kv.second);

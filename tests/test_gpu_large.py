@@ -1,11 +1,14 @@
-"""Full-size parity on frames whose tensors do not fit a host-side oracle run:
-the 8192x8192 mixture frame with B=128 (2^33 entries, 34 GB) and an
+"""Full-size parity on frames whose tensors do not fit a host-side oracle run
+at once: the 8192x8192 mixture frame with B=128 (2^33 entries, 34 GB) and an
 8192x8192 frame with B=64 (exactly 2^32 entries, the 32-bit index boundary).
 
-The oracle computes sampled rows directly from Eq. 1 (row_by_definition) and
-sampled rectangles by counting pixels; properties that hold at any size are
-checked on every entry: the bins of each pixel sum to (x+1)(y+1), and the
-last entry is the frame's histogram.  Tolerance 0 everywhere."""
+Every entry is compared with the oracle: its recursion runs block of rows
+after block of rows (integral_rows, carrying the last row), and each block
+of the device tensor is downloaded when its turn comes.  On top of that,
+rows summed directly from Eq. 1 (row_by_definition), rectangles counted
+pixel by pixel, and properties that hold at any size: the bins of each pixel
+sum to (x+1)(y+1), and the last entry is the frame's histogram.  Tolerance 0
+everywhere."""
 import numpy as np
 import pytest
 
@@ -42,13 +45,16 @@ def check_rows(orc, ih, I, B, rows):
         assert np.array_equal(got, want), f"row {y} differs"
 
 
-def test_mixture_frame_8192_b128(ihb, orc):
+@pytest.mark.timeout(600)
+def test_mixture_frame_8192_b128(ihb, orc, rows_compare):
     from paper_1711_01919_amd import synth
     I, B, rects = synth.mixture_frame()
     H, W = I.shape
     f = torch.from_numpy(I).cuda()
     ih = ihb.compute(f, B)
     torch.cuda.synchronize()
+    diff = rows_compare(orc, ih, I, B)
+    assert diff is None, f"first difference (y, x, b, got, want) = {diff}"
     ok, where = bin_sum_invariant(ih, H, W)
     assert ok, f"bin-sum invariant fails at (y, x) = {where}"
     rng = np.random.default_rng(5)
@@ -74,7 +80,8 @@ def test_mixture_frame_8192_b128(ihb, orc):
     torch.cuda.empty_cache()
 
 
-def test_index_boundary_2_32_entries(ihb, orc):
+@pytest.mark.timeout(600)
+def test_index_boundary_2_32_entries(ihb, orc, rows_compare):
     """8192 x 8192 x 64 = 2^32 entries: offsets past 2^32 elements' worth of
     bytes and the very last entry must land where they belong."""
     rng = np.random.default_rng(9)
@@ -84,6 +91,8 @@ def test_index_boundary_2_32_entries(ihb, orc):
     f = torch.from_numpy(I).cuda()
     ih = ihb.compute(f, B)
     torch.cuda.synchronize()
+    diff = rows_compare(orc, ih, I, B)
+    assert diff is None, f"first difference (y, x, b, got, want) = {diff}"
     ok, where = bin_sum_invariant(ih, H, W)
     assert ok, f"bin-sum invariant fails at (y, x) = {where}"
     check_rows(orc, ih, I, B, [0, 4095, 4096, 8190, H - 1])
@@ -91,9 +100,9 @@ def test_index_boundary_2_32_entries(ihb, orc):
     torch.cuda.empty_cache()
 
 
-def test_batched_large_frames(ihb, orc):
+def test_batched_large_frames(ihb, orc, rows_compare):
     """Two 3840x2160 frames of different bin counts in one batched plan, with
-    the autotuner on; sampled rows against the oracle."""
+    the autotuner on; every entry against the oracle."""
     rng = np.random.default_rng(10)
     frames = [rng.integers(0, 256, size=(2160, 3840), dtype=np.uint8) for _ in range(2)]
     bins = [128, 16]
@@ -103,7 +112,8 @@ def test_batched_large_frames(ihb, orc):
     plan.launch()
     torch.cuda.synchronize()
     for k in range(2):
+        diff = rows_compare(orc, outs[k], frames[k], bins[k])
+        assert diff is None, (k, diff)
         ok, where = bin_sum_invariant(outs[k], 2160, 3840)
         assert ok, (k, where)
-        check_rows(orc, outs[k], frames[k], bins[k], [0, 1079, 2159])
     plan.close()

@@ -75,11 +75,9 @@ def test_tables_change_between_calls_on_one_stream(ihb, orc):
         assert np.array_equal(o.cpu().numpy(), orc.integral_histogram_lut(I, 24, lut))
 
 
-def test_full_hd_table_sampled_rows(ihb, orc):
+def test_full_hd_table(ihb, orc):
     rng = np.random.default_rng(53)
     I = rng.integers(0, 256, size=(1080, 1920), dtype=np.uint8)
     lut = monotone_lut(rng, 64)
     out = ihb.compute_lut(torch.from_numpy(I).cuda(), 64, lut)
-    full = orc.integral_histogram_lut(I, 64, lut)
-    for y in (0, 1, 539, 1078, 1079):
-        assert np.array_equal(out[y].cpu().numpy(), full[y]), y
+    assert np.array_equal(out.cpu().numpy(), orc.integral_histogram_lut(I, 64, lut))
