@@ -474,84 +474,113 @@ def percentiles(xs):
             "mean_ms": float(a.mean()), "max_ms": float(a.max()), "n": int(a.size)}
 
 
-def serving_leg(torch, ihb, synth, seconds: float) -> dict:
-    """16 synthetic video streams with Poisson arrivals at 30-120 fps, each
-    frame followed by 256 rectangle queries, replayed open-loop on the wall
-    clock; first through the serving loop (200 GB budget), then through the
-    plain per-frame path (one host thread, FIFO: upload, ih_compute, ih_query,
-    download, synchronize).  Latency = results in host memory - scheduled
-    arrival, both on the monotonic clock the library also stamps with."""
-    specs = synth.stream_plan(duration_s=seconds)
-    pools = [synth.stream_frame_pool(100 + s, sp, pool=3) for s, sp in enumerate(specs)]
-    events = sorted((float(t), s, k) for s, sp in enumerate(specs) for k, t in enumerate(sp.arrivals))
-    entries = sum(specs[s].H * specs[s].W * specs[s].B for _, s, _ in events)
-
-    # served: a submitting thread replays the arrivals, a polling thread
-    # collects results as they finish (as a client would)
+def serve_trace(ihb, srv, events, pools, specs, speed: float) -> dict:
+    """Replay `events` (arrival seconds, stream, frame index) open-loop at
+    `speed` times their rate through the server: a submitting thread follows
+    the wall clock, a polling thread collects results as a client would.
+    Latency = results in host memory - scheduled arrival, on the monotonic
+    clock the library also stamps with; each request's latency splits into
+    the submitter's lag behind the schedule, the wait for admission and the
+    device part (admission to results in host memory)."""
     import threading
-    srv = ihb.Server(budget_bytes=200 << 30, max_slots=64, n_hip_streams=4, max_batch=16,
-                     pinned_bytes=4 << 30)
-    warm = srv.submit(0, pools[0][0][0], specs[0].B, pools[0][1][0])
-    srv.wait(warm)
-    tickets = [None] * len(events)
-    arrival_ns = [0] * len(events)
-    lag = []
+    n = len(events)
+    tickets = [None] * n
+    due_ns = [0] * n
+    lag = [0.0] * n
+    timing = [None] * n
     submitted = threading.Semaphore(0)
-    lat_served = [0.0] * len(events)
 
     def poller():
-        for i in range(len(events)):
+        for i in range(n):
             submitted.acquire()
-            _, tm = srv.wait(tickets[i], timeout_s=120.0, sleep_s=2e-5)
-            lat_served[i] = (tm["t_done_ns"] - arrival_ns[i]) / 1e6
+            _, tm = srv.wait(tickets[i], timeout_s=300.0, sleep_s=2e-5)
+            timing[i] = tm
 
     th = threading.Thread(target=poller)
     th.start()
     t0 = time.monotonic_ns()
-    for i, (t_arr, s, k) in enumerate(events):
-        due = t0 + int(t_arr * 1e9)
+    for i, (t_arr, sid, k) in enumerate(events):
+        due = t0 + int(t_arr / speed * 1e9)
         now = time.monotonic_ns()
         if now < due:
             time.sleep((due - now) / 1e9)
-        arrival_ns[i] = due
-        lag.append((time.monotonic_ns() - due) / 1e6)
-        f, r = pools[s][0][k % len(pools[s][0])], pools[s][1][k % len(pools[s][1])]
-        tickets[i] = srv.submit(s, f, specs[s].B, r)
+        due_ns[i] = due
+        lag[i] = (time.monotonic_ns() - due) / 1e6
+        f, r = pools[sid][0][k % len(pools[sid][0])], pools[sid][1][k % len(pools[sid][1])]
+        tickets[i] = srv.submit(sid, f, specs[sid].B, r)
         submitted.release()
     th.join()
-    wall_served = (time.monotonic_ns() - t0) / 1e9
-    stats = srv.stats()
-    srv.close()
+    wall = (max(tm["t_done_ns"] for tm in timing) - t0) / 1e9
+    lat = [(tm["t_done_ns"] - due_ns[i]) / 1e6 for i, tm in enumerate(timing)]
+    worst = int(np.argmax(lat))
+    tw = timing[worst]
+    return {"lat": lat, "wall_s": wall,
+            "submit_lag_p99_ms": float(np.percentile(np.asarray(lag), 99)),
+            "worst": {"ms": lat[worst], "submit_lag_ms": lag[worst],
+                      "admission_wait_ms": (tw["t_admit_ns"] - tw["t_submit_ns"]) / 1e6,
+                      "device_ms": (tw["t_done_ns"] - tw["t_admit_ns"]) / 1e6}}
 
-    # plain per-frame path
+
+def plain_trace(torch, ihb, events, pools, specs, speed: float, outs) -> dict:
+    """The same arrivals through the plain per-frame path: one host thread,
+    FIFO; per frame upload, ih_compute, ih_query, download, synchronize."""
     dev = torch.device("cuda:0")
+    lat = []
+    t0 = time.monotonic_ns()
+    for t_arr, sid, k in events:
+        due = t0 + int(t_arr / speed * 1e9)
+        now = time.monotonic_ns()
+        if now < due:
+            time.sleep((due - now) / 1e9)
+        sp = specs[sid]
+        f = torch.from_numpy(pools[sid][0][k % len(pools[sid][0])]).to(dev)
+        ih = ihb.compute(f, sp.B, out=outs[(sp.H, sp.W, sp.B)])
+        ihb.query(ih, pools[sid][1][k % len(pools[sid][1])]).cpu()
+        lat.append((time.monotonic_ns() - due) / 1e6)
+    return {"lat": lat, "wall_s": (time.monotonic_ns() - t0) / 1e9}
+
+
+def serving_leg(torch, ihb, synth, seconds: float) -> dict:
+    """16 synthetic video streams with Poisson arrivals at 30-120 fps, each
+    frame followed by 256 rectangle queries: the trace replayed at 1x, 4x and
+    16x its arrival rate, through the serving loop (200 GB budget) and through
+    the plain per-frame path.  The sweep stops at the first error."""
+    sys.setswitchinterval(5e-4)          # the submitting and polling threads share the interpreter
+    specs = synth.stream_plan(duration_s=seconds)
+    pools = [synth.stream_frame_pool(100 + s, sp, pool=3) for s, sp in enumerate(specs)]
+    events = sorted((float(t), s, k) for s, sp in enumerate(specs) for k, t in enumerate(sp.arrivals))
+    entries = sum(specs[s].H * specs[s].W * specs[s].B for _, s, _ in events)
     outs = {}
     for sp in specs:
         key = (sp.H, sp.W, sp.B)
         if key not in outs:
-            outs[key] = torch.empty(key, dtype=torch.uint32, device=dev)
-    lat_plain = []
-    t0 = time.monotonic_ns()
-    for t_arr, s, k in events:
-        due = t0 + int(t_arr * 1e9)
-        now = time.monotonic_ns()
-        if now < due:
-            time.sleep((due - now) / 1e9)
-        sp = specs[s]
-        f = torch.from_numpy(pools[s][0][k % len(pools[s][0])]).to(dev)
-        ih = ihb.compute(f, sp.B, out=outs[(sp.H, sp.W, sp.B)])
-        h = ihb.query(ih, pools[s][1][k % len(pools[s][1])]).cpu()
-        lat_plain.append((time.monotonic_ns() - due) / 1e6)
-    wall_plain = (time.monotonic_ns() - t0) / 1e9
+            outs[key] = torch.empty(key, dtype=torch.uint32, device="cuda")
+    srv = ihb.Server(budget_bytes=200 << 30, max_slots=64, n_hip_streams=4, max_batch=16,
+                     pinned_bytes=24 << 30)
+    warm = srv.submit(0, pools[0][0][0], specs[0].B, pools[0][1][0])
+    srv.wait(warm)
+    res = {"workload": f"{len(specs)} streams, {len(events)} frames ({entries:.3g} entries) over {seconds:.0f} s "
+                       f"at 1x, 256 queries per frame", "rates": {}}
+    try:
+        for speed in (1, 4, 16):
+            srv_before = srv.stats()
+            sv = serve_trace(ihb, srv, events, pools, specs, float(speed))
+            st = srv.stats()
+            pl = plain_trace(torch, ihb, events, pools, specs, float(speed), outs)
+            res["rates"][f"{speed}x"] = {
+                "offered_entries_per_s": entries / (seconds / speed),
+                "served": {**percentiles(sv["lat"]), "entries_per_s": entries / sv["wall_s"],
+                           "submit_lag_p99_ms": sv["submit_lag_p99_ms"], "worst": sv["worst"],
+                           "device_bytes_peak": st["device_bytes_peak"],
+                           "budget_blocked": st["budget_blocked"] - srv_before["budget_blocked"]},
+                "plain_loop": {**percentiles(pl["lat"]), "entries_per_s": entries / pl["wall_s"]}}
+            log(f"[bench] serving at {speed}x: {res['rates'][f'{speed}x']}")
+    except Exception as e:                                   # the sweep stops at the first error
+        res["error"] = f"{type(e).__name__}: {e}"
+    srv.close()
     del outs
     torch.cuda.empty_cache()
-    return {
-        "workload": f"{len(specs)} streams, {len(events)} frames over {seconds:.0f} s, 256 queries per frame",
-        "served": {**percentiles(lat_served), "entries_per_s": entries / wall_served,
-                   "submit_lag_p99_ms": float(np.percentile(np.asarray(lag), 99)),
-                   "device_bytes_peak": stats["device_bytes_peak"], "budget_blocked": stats["budget_blocked"]},
-        "plain_loop": {**percentiles(lat_plain), "entries_per_s": entries / wall_plain},
-    }
+    return res
 
 
 def main():

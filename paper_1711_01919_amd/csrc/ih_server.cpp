@@ -21,12 +21,14 @@
 #include <array>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <list>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <string>
@@ -46,14 +48,16 @@ uint64_t now_ns()
 constexpr size_t kAlign = 256;
 
 // Pinned host staging: one block allocated on first use and carved by an
-// Arena; requests that do not fit it fall back to recycled size-class buffers.
+// Arena; requests that do not fit it fall back to recycled size-class
+// buffers, pinned when the runtime can pin them and ordinary (pageable,
+// copied through the runtime's staging) when it cannot.
 class PinnedPool {
 public:
     explicit PinnedPool(size_t arena_bytes = 0) : arena_bytes_(arena_bytes) {}
     ~PinnedPool()
     {
         for (auto& kv : free_)
-            for (void* p : kv.second) (void)hipHostFree(p);
+            for (void* p : kv.second) release_buffer(p);
         if (base_) (void)hipHostFree(base_);
     }
     void set_arena_bytes(size_t b) { arena_bytes_ = b; }
@@ -88,7 +92,8 @@ public:
         void* p = nullptr;
         if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
-            return nullptr;
+            p = std::malloc(c);
+            if (p) pageable_.insert(p);
         }
         return p;
     }
@@ -109,7 +114,18 @@ public:
     }
 
 private:
+    void release_buffer(void* p)
+    {
+        auto it = pageable_.find(p);
+        if (it == pageable_.end()) {
+            (void)hipHostFree(p);
+        } else {
+            std::free(p);
+            pageable_.erase(it);
+        }
+    }
     std::mutex mu_;
+    std::set<void*> pageable_;                 // size-class buffers the runtime could not pin
     size_t arena_bytes_ = 0;
     bool tried_ = false;
     void* base_ = nullptr;

@@ -2,6 +2,7 @@
 point that include/ih.h declares, and rejects bad arguments before touching
 the device (no call here reaches a kernel)."""
 import ctypes
+import os
 import re
 from pathlib import Path
 
@@ -9,7 +10,9 @@ import pytest
 
 ROOT = Path(__file__).resolve().parent.parent
 HEADER = ROOT / "include" / "ih.h"
-LIB = ROOT / "paper_1711_01919_amd" / "libih.so"
+# IH_LIBRARY may name another build of the same library (the sanitized
+# builds of tests/test_host_checks.py run this file against theirs).
+LIB = Path(os.environ.get("IH_LIBRARY", ROOT / "paper_1711_01919_amd" / "libih.so"))
 
 
 def declared_functions():
