@@ -96,12 +96,14 @@ ih_status ih_compute_binmajor(const uint8_t* frame, int32_t H, int32_t W, int32_
  * ih_compute_lut -- as ih_compute, with the bins given by a table: the pixel
  * of value v counts in bin lut_host[v].  The paper states the binning only as
  * membership of a pixel value in a bin (Sec. 2.1, the Q of Eq. 1); a table
- * gives bins of arbitrary edges.  lut_host: 256 host bytes, each below B and
- * never decreasing (lut_host[v] <= lut_host[v+1]), so every bin is one range
- * of values, possibly empty.  The table is copied before the call returns
- * (the caller may reuse it at once); the kernels are asynchronous on stream.
- * Errors: as ih_compute, and IH_ERR_INVALID_ARG for a null table, an entry
- * >= B or a decreasing table (checked before anything is launched).
+ * gives bins of arbitrary edges, or any other membership (a bin may hold
+ * values from several ranges, or none).  lut_host: 256 host bytes, each below
+ * B.  A non-decreasing table (every bin one range of values) takes a range
+ * test per bin; any other table bins each pixel through the table first.
+ * The table is copied before the call returns (the caller may reuse it at
+ * once); the kernels are asynchronous on stream.  Errors: as ih_compute, and
+ * IH_ERR_INVALID_ARG for a null table or an entry >= B (checked before
+ * anything is launched).
  */
 ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, const uint8_t* lut_host,
                          uint32_t* out, ih_stream_t stream);
@@ -159,9 +161,9 @@ typedef struct {
     int32_t H, W, B;
     const uint8_t* lut;         /* host, NULL for the uniform bins, else a bin
                                    table as for ih_compute_lut (256 entries,
-                                   non-decreasing, each < B), copied when the
-                                   plan is created; such frames take tiles at
-                                   most 64 wide and are not autotuned         */
+                                   each < B), copied when the plan is
+                                   created; such frames take tiles at most
+                                   64 wide and are not autotuned             */
     int32_t binmajor;           /* 0: out in H x W x B; 1: out in the bin-major
                                    b x h x w layout of ih_compute_binmajor
                                    (uniform bins only: lut must be NULL; such
@@ -347,7 +349,7 @@ ih_status ih_submit(ih_server* server, int32_t stream_id, const uint8_t* frame_h
 /*
  * ih_submit_lut -- as ih_submit, with each pixel value v counted in bin
  * lut_host[v] instead of Q(v) (the bin test of Eq. 1 as a table; HOST, 256
- * entries, non-decreasing, each below B, copied before the call returns).
+ * entries, each below B, copied before the call returns).
  * Requests with and without tables share batches.  Errors: those of
  * ih_submit, and IH_ERR_INVALID_ARG for a null or invalid table.
  */

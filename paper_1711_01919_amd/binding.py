@@ -193,7 +193,7 @@ def compute_binmajor(frame: torch.Tensor, B: int, out: torch.Tensor | None = Non
 
 def compute_lut(frame: torch.Tensor, B: int, lut, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """ih_compute_lut: the integral histogram with bins given by a table
-    (pixel value v counts in bin lut[v]; 256 non-decreasing entries below B)."""
+    (pixel value v counts in bin lut[v]; 256 entries below B, in any order)."""
     if frame.dtype != torch.uint8 or frame.dim() != 2 or not frame.is_cuda or not frame.is_contiguous():
         raise ValueError("frame must be a contiguous 2-D uint8 CUDA tensor")
     table = np.ascontiguousarray(lut, dtype=np.uint8)

@@ -41,7 +41,7 @@ struct ih_batch_plan {
     std::vector<ih::TileChoice> tiles;
     void* d_scratch = nullptr;
     void* d_image = nullptr;
-    std::vector<uint8_t> luts;            // copies of the frames' bin tables, 256 bytes each
+    std::vector<uint8_t> luts;            // copies of the frames' bin tables, 256 bytes each (any entries < B)
     std::vector<int32_t> lut_index;       // per frame: index into luts, or -1 (uniform bins)
     void* d_luts = nullptr;
     ih::BatchImage image;                 // one group: every frame
@@ -164,8 +164,9 @@ ih_status build_plan(ih_batch_plan* p)
         bm[k] = p->descs[k].binmajor ? 1 : 0;
         const int32_t li = p->lut_index.empty() ? -1 : p->lut_index[k];
         const uint8_t* dl = li < 0 ? nullptr : static_cast<const uint8_t*>(p->d_luts) + (size_t)li * 256;
+        const bool general = li >= 0 && ih::lut_is_general(p->luts.data() + (size_t)li * 256);
         frames[k] = ih::frame_args(p->descs[k].frame, p->descs[k].out,
-                                   static_cast<uint32_t*>(p->d_scratch) + off[k], geoms[k], dl);
+                                   static_cast<uint32_t*>(p->d_scratch) + off[k], geoms[k], dl, general);
         nt[k] = p->tiles[k].nontemporal ? 1 : 0;
         total_out += (int64_t)p->descs[k].H * p->descs[k].W * p->descs[k].B * 4;
     }
@@ -500,12 +501,9 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
         if (d.lut) {
             if (forced && o.tile_x > 64)
                 return fail(IH_ERR_INVALID_ARG, "frame %zu: bin tables take tiles at most 64 wide", k);
-            for (int v = 0; v < 256; ++v) {
+            for (int v = 0; v < 256; ++v)
                 if ((int32_t)d.lut[v] >= d.B)
                     return fail(IH_ERR_INVALID_ARG, "frame %zu: lut[%d]=%d is not a bin below B=%d", k, v, d.lut[v], d.B);
-                if (v > 0 && d.lut[v] < d.lut[v - 1])
-                    return fail(IH_ERR_INVALID_ARG, "frame %zu: lut decreases at %d", k, v);
-            }
         }
     }
     ih_batch_plan* p = new ih_batch_plan;

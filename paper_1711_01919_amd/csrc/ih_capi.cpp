@@ -71,9 +71,10 @@ ih_status get_scratch(hipStream_t stream, size_t bytes, void** out)
 
 // The three phases of one frame on one stream, timed when profiling is on.
 ih_status enqueue_frame(const uint8_t* frame, uint32_t* out, uint32_t* scratch,
-                        const ih::Geom& g, bool nt, hipStream_t s, const uint8_t* lut = nullptr)
+                        const ih::Geom& g, bool nt, hipStream_t s, const uint8_t* lut = nullptr,
+                        bool lut_general = false)
 {
-    const ih::FrameArgs fa = ih::frame_args(frame, out, scratch, g, lut);
+    const ih::FrameArgs fa = ih::frame_args(frame, out, scratch, g, lut, lut_general);
     ih::PhaseTimer timer;
     for (int ph = 0; ph < ih::kNumPhases; ++ph) {
         if (ih_status st = timer.begin(ph, s)) return st;
@@ -206,12 +207,9 @@ ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, 
     if (!frame || !out || !lut_host) return fail(IH_ERR_INVALID_ARG, "frame, lut and out must be non-null");
     if (ih_status st = ih::check_shape(H, W, B)) return st;
     if (reinterpret_cast<uintptr_t>(out) & 3u) return fail(IH_ERR_INVALID_ARG, "out must be 4-byte aligned");
-    for (int v = 0; v < 256; ++v) {
+    for (int v = 0; v < 256; ++v)
         if ((int32_t)lut_host[v] >= B)
             return fail(IH_ERR_INVALID_ARG, "lut[%d]=%d is not a bin below B=%d", v, lut_host[v], B);
-        if (v > 0 && lut_host[v] < lut_host[v - 1])
-            return fail(IH_ERR_INVALID_ARG, "lut decreases at %d (%d after %d)", v, lut_host[v], lut_host[v - 1]);
-    }
     const ih::TileChoice t = ih::default_tile(H, W, B);
     const ih::Geom g = ih::make_geom(H, W, B, t);
     const size_t carry_bytes = (ih::scratch_layout(g).words * sizeof(uint32_t) + 255) / 256 * 256;
@@ -224,7 +222,7 @@ ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, 
     hipError_t e = ih::launch_lut_store(lut_host, dlut, s);
     if (e != hipSuccess) return hip_fail(e, "bin table upload");
     return enqueue_frame(frame, out, static_cast<uint32_t*>(scratch), g, t.nontemporal, s,
-                         reinterpret_cast<const uint8_t*>(dlut));
+                         reinterpret_cast<const uint8_t*>(dlut), ih::lut_is_general(lut_host));
 }
 
 ih_status ih_write_reference(uint32_t* out, int32_t H, int32_t W, int32_t B, int32_t tile_x, int32_t tile_y,

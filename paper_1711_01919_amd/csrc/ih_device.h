@@ -61,8 +61,8 @@ __device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs,
 }
 
 // Bin of a pixel value.  A frame either uses the uniform bins floor(v B / 256)
-// or a table of 256 bins (non-decreasing, so each bin is one value range),
-// which the count kernels stage in LDS, four entries per word.
+// or a table of 256 bins, which the count kernels stage in LDS, four entries
+// per word.
 __device__ __forceinline__ void stage_lut(const FrameArgs& f, uint32_t* lutw, int tid, int nthreads)
 {
     if (f.lut)

@@ -18,11 +18,18 @@ ScratchLayout scratch_layout(const Geom& g)
 }
 
 FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g,
-                     const uint8_t* lut)
+                     const uint8_t* lut, bool lut_general)
 {
     const ScratchLayout sl = scratch_layout(g);
     return FrameArgs{frame, out, scratch + sl.rowc, scratch + sl.colc, scratch + sl.corner, scratch + sl.cnt,
-                     lut, g};
+                     lut, lut && lut_general ? 1 : 0, g};
+}
+
+bool lut_is_general(const uint8_t* lut_host)
+{
+    for (int v = 1; v < 256; ++v)
+        if (lut_host[v] < lut_host[v - 1]) return true;
+    return false;
 }
 
 bool fused_supported(const Geom& g)

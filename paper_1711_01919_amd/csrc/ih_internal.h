@@ -66,11 +66,14 @@ struct FrameArgs {
     uint32_t* colc;
     uint32_t* corner;
     uint32_t* cnt;
-    const uint8_t* lut;      // device bin table (256 entries, non-decreasing, < B); null: floor(v B / 256)
+    const uint8_t* lut;      // device bin table (256 entries, each < B); null: floor(v B / 256)
+    int32_t lut_general;     // 1: the table decreases somewhere (a bin need not be one range of values)
     Geom g;
 };
 FrameArgs frame_args(const uint8_t* frame, uint32_t* out, uint32_t* scratch, const Geom& g,
-                     const uint8_t* lut = nullptr);
+                     const uint8_t* lut = nullptr, bool lut_general = false);
+// Whether a host bin table decreases somewhere.
+bool lut_is_general(const uint8_t* lut_host);
 
 // A job maps a contiguous range of a batched launch -- blocks for the count
 // and scan kernels, work items (one per wave) for the tile kernel -- to one

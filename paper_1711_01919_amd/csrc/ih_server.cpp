@@ -320,7 +320,8 @@ hipError_t enqueue_frames(ih_server* s, Batch& bt, hipStream_t st)
             e = hipMemsetAsync(w.scratch, 0, (size_t)ih::kCounterWords * sizeof(uint32_t), st);
         if (e != hipSuccess) return e;
         frames.push_back(ih::frame_args(w.frame, d_out, w.scratch, r.geom,
-                                        r.has_lut ? reinterpret_cast<const uint8_t*>(w.lut) : nullptr));
+                                        r.has_lut ? reinterpret_cast<const uint8_t*>(w.lut) : nullptr,
+                                        r.has_lut && ih::lut_is_general(r.lut)));
         nt.push_back(0);
     }
     ih::BatchImage img;
@@ -614,12 +615,9 @@ ih_status submit_request(ih_server* s, int32_t stream_id, const uint8_t* frame_h
         if (q.x0 < 0 || q.x0 > q.x1 || q.x1 >= W || q.y0 < 0 || q.y0 > q.y1 || q.y1 >= H)
             return fail(IH_ERR_INVALID_ARG, "rectangle %zu is outside the %dx%d frame", r, W, H);
     }
-    for (int v = 0; lut_host && v < 256; ++v) {
+    for (int v = 0; lut_host && v < 256; ++v)
         if ((int32_t)lut_host[v] >= B)
             return fail(IH_ERR_INVALID_ARG, "lut[%d]=%d is not a bin below B=%d", v, lut_host[v], B);
-        if (v > 0 && lut_host[v] < lut_host[v - 1])
-            return fail(IH_ERR_INVALID_ARG, "lut decreases at %d (%d after %d)", v, lut_host[v], lut_host[v - 1]);
-    }
     auto r = std::make_shared<Request>();
     r->stream_id = stream_id;
     r->H = H; r->W = W; r->B = B; r->nq = nq;

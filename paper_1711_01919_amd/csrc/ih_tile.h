@@ -92,6 +92,19 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
     const int L = BC ? LC : g.L;
     const int S = BC ? kWave / LC : g.S;
 
+    // A table that decreases somewhere (a bin need not be one range of
+    // values): every pixel of a row is binned through the table, staged in
+    // this wave's LDS, before the lanes test their bins (q == b).
+    __shared__ uint32_t lut_lds[kWavesPerBlock][kWave];
+    uint32_t* lutw = nullptr;
+    if constexpr (TABLE) {
+        if (f.lut_general) {
+            lutw = lut_lds[wave_in_block()];
+            lutw[lane] = reinterpret_cast<const IH_GLOBAL uint32_t*>(gmem(f.lut))[lane];
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
     const int s = lane / L;
     const int b0 = (lane - s * L) * BPL;
     const int j = jg * S + s;
@@ -103,9 +116,9 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
 
     // Bin b holds the values v in [lo, lo + width).  Uniform bins: v with
     // ceil(256 b / B) <= v < ceil(256 (b+1) / B), which is floor(v B / 256)
-    // == b.  A bin table: lo = #{v : lut[v] < b}, lo + width = #{v : lut[v]
-    // <= b} (the table never decreases).  A lane tests v - lo < width
-    // (unsigned); an empty bin has width 0.
+    // == b.  A non-decreasing bin table: lo = #{v : lut[v] < b}, lo + width =
+    // #{v : lut[v] <= b}.  A lane tests v - lo < width (unsigned); an empty
+    // bin has width 0.  Any other table: v is the pixel's bin, lo = b, width 1.
     uint32_t lo[BPL], wd[BPL];
     bool bvalid[BPL];
 #pragma unroll
@@ -114,8 +127,11 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
         const IH_GLOBAL uint8_t* lt = gmem(f.lut);
 #pragma unroll
         for (int t = 0; t < BPL; ++t) {
-            const uint32_t l = lut_count_below(lt, (uint32_t)(b0 + t));
-            const uint32_t h = lut_count_below(lt, (uint32_t)(b0 + t + 1));
+            uint32_t l = (uint32_t)(b0 + t), h = l + 1;
+            if (!lutw) {
+                l = lut_count_below(lt, (uint32_t)(b0 + t));
+                h = lut_count_below(lt, (uint32_t)(b0 + t + 1));
+            }
             lo[t] = bvalid[t] ? l : 0u;
             wd[t] = bvalid[t] ? h - l : 0u;
         }
@@ -193,8 +209,26 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
     const bool vec_ok = (b0 + BPL <= B) && (B % BPL == 0) &&
                         ((reinterpret_cast<uintptr_t>(f.out) & (4 * BPL - 1)) == 0);
 
-    auto row_pass = [&](int y, const uint32_t (&px)[TX / 4], const uint32_t (&c0)[BPL]) {
+    auto row_pass = [&](int y, const uint32_t (&px_in)[TX / 4], const uint32_t (&c0)[BPL]) {
         IH_GLOBAL uint32_t* orow = gmem(f.out) + ((size_t)y * g.W + x0) * B + b0;
+        uint32_t px[TX / 4];
+#pragma unroll
+        for (int q = 0; q < TX / 4; ++q) px[q] = px_in[q];
+        if constexpr (TABLE) {
+            if (lutw) {
+                // bin every pixel of the row through the table
+#pragma unroll
+                for (int q = 0; q < TX / 4; ++q) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const uint32_t v = (px[q] >> (8 * e)) & 0xFFu;
+                        w |= ((lutw[v >> 2] >> (8 * (v & 3u))) & 0xFFu) << (8 * e);
+                    }
+                    px[q] = w;
+                }
+            }
+        }
         uint32_t cnt[BPL];
 #pragma unroll
         for (int t = 0; t < BPL; ++t) cnt[t] = c0[t];

@@ -106,11 +106,11 @@ def test_compute_lut_rejects_bad_tables_before_launch(lib):
     fake = 0x1000  # never dereferenced: validation fails first
     good = (ctypes.c_uint8 * 256)(*[v * 4 // 256 for v in range(256)])
     too_big = (ctypes.c_uint8 * 256)(*([0] * 255 + [4]))
-    decreasing = (ctypes.c_uint8 * 256)(*([1] * 128 + [0] * 128))
+    decreasing_too_big = (ctypes.c_uint8 * 256)(*([5] * 128 + [0] * 128))
     assert f(fake, 4, 4, 4, None, fake, None) == 1
     assert f(None, 4, 4, 4, good, fake, None) == 1
     assert f(fake, 4, 4, 4, too_big, fake, None) == 1
-    assert f(fake, 4, 4, 4, decreasing, fake, None) == 1
+    assert f(fake, 4, 4, 4, decreasing_too_big, fake, None) == 1
     assert f(fake, 0, 4, 4, good, fake, None) == 1
     assert f(fake, 4, 4, 4, good, fake + 2, None) == 1
 
@@ -124,10 +124,10 @@ def test_batch_plan_rejects_bad_tables_and_layouts_before_launch(lib):
     f.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.POINTER(ctypes.c_void_p)]
     fake = 0x1000  # never dereferenced: validation fails first
-    decreasing = (ctypes.c_uint8 * 256)(*([2] * 100 + [1] * 156))
     too_big = (ctypes.c_uint8 * 256)(*([0] * 255 + [8]))
+    decreasing_too_big = (ctypes.c_uint8 * 256)(*([9] * 100 + [1] * 156))
     plan = ctypes.c_void_p()
-    for table in (decreasing, too_big):
+    for table in (decreasing_too_big, too_big):
         d = (FrameDesc * 1)(FrameDesc(fake, fake, 4, 4, 8, ctypes.cast(table, ctypes.c_void_p), 0))
         assert f(d, 1, None, None, ctypes.byref(plan)) == 1
         assert not plan.value

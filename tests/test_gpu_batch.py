@@ -323,10 +323,10 @@ def test_bad_descriptors_rejected(ihb):
 
 @pytest.mark.parametrize("group_bytes,use_graph,autotune", [(0, True, False), (40 << 20, True, False), (0, False, True)])
 def test_plan_with_bin_tables(ihb, orc, group_bytes, use_graph, autotune):
-    """Frames with bin tables next to frames with uniform bins in one plan
-    (graphed, pipelined, autotuned): each equals the oracle's result for its
-    binning; the tables are copied at creation (the caller's are overwritten
-    right after)."""
+    """Frames with bin tables (non-decreasing, and in any order) next to frames
+    with uniform bins in one plan (graphed, pipelined, autotuned): each equals
+    the oracle's result for its binning; the tables are copied at creation
+    (the caller's are overwritten right after)."""
     rng = np.random.default_rng(26)
     shapes = [(240, 320, 64), (97, 203, 32), (360, 640, 16), (61, 64, 128), (240, 320, 64), (130, 257, 7),
               (480, 640, 64)]
@@ -334,9 +334,11 @@ def test_plan_with_bin_tables(ihb, orc, group_bytes, use_graph, autotune):
     bins = [b for _, _, b in shapes]
     luts = []
     for k, b in enumerate(bins):
-        if k % 2 == 0:
+        if k % 4 == 0:
             edges = np.sort(rng.integers(0, 257, size=b - 1))
             luts.append(np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8))
+        elif k % 4 == 2:
+            luts.append(rng.integers(0, b, size=256).astype(np.uint8))        # any order
         else:
             luts.append(None)
     refs = [orc.integral_histogram(f, b) if t is None else orc.integral_histogram_lut(f, b, t)

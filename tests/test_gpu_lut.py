@@ -1,6 +1,7 @@
 """Bins given by a table (ih_compute_lut): the pixel of value v counts in bin
-lut[v], with 256 non-decreasing entries below B -- bins of arbitrary edges,
-some possibly empty.  Bit-exact against the oracle's table recursion
+lut[v], with 256 entries below B -- non-decreasing tables (bins of arbitrary
+edges, some possibly empty) and tables in any order (a bin holding values
+from several ranges).  Bit-exact against the oracle's table recursion
 (tolerance 0) on ragged shapes that span several tiles, and the uniform table
 gives exactly ih_compute's result."""
 import numpy as np
@@ -81,3 +82,53 @@ def test_full_hd_table(ihb, orc):
     lut = monotone_lut(rng, 64)
     out = ihb.compute_lut(torch.from_numpy(I).cuda(), 64, lut)
     assert np.array_equal(out.cpu().numpy(), orc.integral_histogram_lut(I, 64, lut))
+
+
+def general_lut(rng, B):
+    """A table in any order: every entry drawn uniformly below B."""
+    return rng.integers(0, B, size=256).astype(np.uint8)
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 16, 32, 64, 100, 128, 256])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_general_tables_equal_oracle(ihb, orc, B, shape):
+    H, W = shape
+    rng = np.random.default_rng(B * 104729 + H * 37 + W)
+    I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    lut = general_lut(rng, B)
+    out = ihb.compute_lut(torch.from_numpy(I).cuda(), B, lut)
+    assert np.array_equal(out.cpu().numpy(), orc.integral_histogram_lut(I, B, lut))
+
+
+def test_general_table_structures(ihb, orc):
+    """Tables that are not one range per bin: alternating bins (odd and even
+    values), a bin holding the two ends of the range, a reversed table."""
+    rng = np.random.default_rng(55)
+    I = rng.integers(0, 256, size=(257, 333), dtype=np.uint8)
+    v = np.arange(256)
+    tables = [(2, (v % 2).astype(np.uint8)),
+              (3, np.where((v < 40) | (v > 215), 2, v * 2 // 256).astype(np.uint8)),
+              (64, (63 - (v * 64 >> 8)).astype(np.uint8)),
+              (256, rng.permutation(256).astype(np.uint8))]
+    for B, lut in tables:
+        out = ihb.compute_lut(torch.from_numpy(I).cuda(), B, lut)
+        assert np.array_equal(out.cpu().numpy(), orc.integral_histogram_lut(I, B, lut)), B
+
+
+def test_full_hd_general_table(ihb, orc):
+    rng = np.random.default_rng(56)
+    I = rng.integers(0, 256, size=(1080, 1920), dtype=np.uint8)
+    lut = general_lut(rng, 64)
+    out = ihb.compute_lut(torch.from_numpy(I).cuda(), 64, lut)
+    assert np.array_equal(out.cpu().numpy(), orc.integral_histogram_lut(I, 64, lut))
+
+
+def test_general_and_monotone_tables_alternate_on_one_stream(ihb, orc):
+    rng = np.random.default_rng(57)
+    I = rng.integers(0, 256, size=(200, 300), dtype=np.uint8)
+    f = torch.from_numpy(I).cuda()
+    luts = [general_lut(rng, 24) if k % 2 else monotone_lut(rng, 24) for k in range(6)]
+    outs = [ihb.compute_lut(f, 24, lut) for lut in luts]
+    torch.cuda.synchronize()
+    for lut, o in zip(luts, outs):
+        assert np.array_equal(o.cpu().numpy(), orc.integral_histogram_lut(I, 24, lut))

@@ -81,9 +81,11 @@ def test_bin_tables_in_mixed_batches(ihb, orc):
         I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
         rects = synth.random_rects(rng, H, W, int(rng.integers(1, 50)))
         lut = None
-        if k % 2 == 0:
+        if k % 4 == 0:
             edges = np.sort(rng.integers(0, 257, size=B - 1))
             lut = np.searchsorted(edges, np.arange(256), side="right").astype(np.uint8)
+        elif k % 4 == 2:
+            lut = rng.integers(0, B, size=256).astype(np.uint8)              # any order
         reqs.append((k % 4, I, B, rects, lut))
     results = {}
     for cfg in (dict(max_slots=1, n_hip_streams=1, max_batch=1), dict(max_slots=16, n_hip_streams=3, max_batch=6)):

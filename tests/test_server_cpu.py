@@ -38,13 +38,15 @@ def test_submit_validation(server):
 def test_submit_rejects_bad_tables(server):
     f = np.zeros((16, 16), np.uint8)
     ok = np.repeat(np.arange(8, dtype=np.uint8), 32)
-    for bad in (np.where(np.arange(256) == 100, 0, ok).astype(np.uint8),     # decreases
-                np.minimum(ok + 1, 8).astype(np.uint8)):                       # entry 8 with B = 8
+    for bad in (np.minimum(ok + 1, 8).astype(np.uint8),                        # entry 8 with B = 8
+                np.where(np.arange(256) == 100, 9, ok[::-1]).astype(np.uint8)):  # any order, but 9 >= B
         with pytest.raises(ihb.IHError) as e:
             server.submit(0, f, 8, lut=bad)
         assert e.value.status == 1
     with pytest.raises(ValueError):
         server.submit(0, f, 8, lut=ok[:255])
+    # a table in any order, each entry below B, is accepted
+    assert server.submit(0, f, 8, lut=ok[::-1].copy()) > 0
 
 
 def test_request_larger_than_budget(server):
