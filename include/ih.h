@@ -109,6 +109,29 @@ ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, 
                          uint32_t* out, ih_stream_t stream);
 
 /*
+ * ih_compute_noalloc -- ih_compute for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, tile choice, kernels and result as
+ * ih_compute; the call itself allocates nothing (no hipMalloc, no hipFree,
+ * no allocating library routine).
+ *
+ * The carries live in a fixed array of IH_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held from the first call on that GPU until the
+ * process ends.  Every call on a GPU shares that GPU's array and leaves its
+ * carries in it: calls on one GPU whose work overlaps (different streams
+ * without ordering between them, or several host threads) race and give
+ * undefined results; calls ordered on one stream are safe.
+ *
+ * Errors: as ih_compute, and IH_ERR_RANGE (nothing launched) when the
+ * frame's carries exceed the array.  Every frame of at most 3840 x 2160
+ * pixels fits at B <= 64; at larger B it depends on the tile ih_compute
+ * picks (1920 x 1080 at B = 128 fits, 1280 x 720 at B = 128 does not).
+ */
+#define IH_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ih_status ih_compute_noalloc(const uint8_t* frame, int32_t H, int32_t W, int32_t B, uint32_t* out,
+                             ih_stream_t stream);
+
+/*
  * ih_query -- region histograms by the four-corner rule (Sec. 2.1, Eq. 2):
  *
  *   h(R, b) = H(x1, y1, b) - H(x0-1, y1, b) - H(x1, y0-1, b) + H(x0-1, y0-1, b)

@@ -99,6 +99,8 @@ def _load() -> ctypes.CDLL:
     lib.ih_compute_binmajor.restype = ctypes.c_int
     lib.ih_compute_lut.argtypes = [vp, i32, i32, i32, vp, vp, vp]
     lib.ih_compute_lut.restype = ctypes.c_int
+    lib.ih_compute_noalloc.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.ih_compute_noalloc.restype = ctypes.c_int
     lib.ih_query.argtypes = [ctypes.POINTER(View), vp, sz, vp]
     lib.ih_query_device.argtypes = [ctypes.POINTER(View), vp, sz, vp, vp]
     lib.ih_query_binmajor.argtypes = [ctypes.POINTER(View), vp, sz, vp]
@@ -173,6 +175,20 @@ def compute(frame: torch.Tensor, B: int, out: torch.Tensor | None = None, stream
     elif out.dtype != torch.uint32 or not out.is_contiguous() or out.numel() < H * W * B:
         raise ValueError("out must be a contiguous uint32 tensor with H*W*B elements")
     _check(lib.ih_compute(_ptr(frame), H, W, B, _ptr(out), _stream_handle(stream)), "ih_compute")
+    return out
+
+
+def compute_noalloc(frame: torch.Tensor, B: int, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """ih_compute_noalloc: as compute(), into a caller-given out, with the
+    carries in the library's fixed per-GPU array (the call allocates no
+    device memory)."""
+    if frame.dtype != torch.uint8 or frame.dim() != 2 or not frame.is_cuda or not frame.is_contiguous():
+        raise ValueError("frame must be a contiguous 2-D uint8 CUDA tensor")
+    H, W = frame.shape
+    if out.dtype != torch.uint32 or not out.is_cuda or not out.is_contiguous() or out.numel() < H * W * B:
+        raise ValueError("out must be a contiguous uint32 CUDA tensor with H*W*B elements")
+    _check(lib.ih_compute_noalloc(_ptr(frame), H, W, int(B), _ptr(out), _stream_handle(stream)),
+           "ih_compute_noalloc")
     return out
 
 

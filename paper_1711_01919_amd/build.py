@@ -46,6 +46,7 @@ SOURCES = {
     "ih_tile_nontemporal.hip": HIP,
     "ih_tile_nontemporal_guarded.hip": HIP,
     "ih_tile_table.hip": HIP,
+    "ih_noalloc.hip": HIP,
     "ih_capi.cpp": HOST,
     "ih_batch.cpp": HOST,
     "ih_util.cpp": HOST,

@@ -62,6 +62,22 @@ def test_compute_rejects_bad_arguments_before_launch(lib):
     assert f(fake, 4, 4, 8, fake + 2, None) == 1              # misaligned output
 
 
+def test_compute_noalloc_rejects_before_touching_the_device(lib):
+    """Argument errors, and frames whose carries exceed the fixed array
+    (IH_ERR_RANGE), come back before any HIP call."""
+    f = lib.ih_compute_noalloc
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    fake = 0x1000  # never dereferenced: validation fails first
+    assert f(None, 4, 4, 8, fake, None) == 1
+    assert f(fake, 4, 4, 8, None, None) == 1
+    assert f(fake, 0, 4, 8, fake, None) == 1
+    assert f(fake, 4, 4, 257, fake, None) == 1
+    assert f(fake, 4, 4, 8, fake + 2, None) == 1
+    assert f(fake, 65536, 65536, 8, fake, None) == 2           # H*W = 2^32
+    assert f(fake, 720, 1280, 128, fake, None) == 2           # carries beyond the array
+    assert f(fake, 2160, 3840, 128, fake, None) == 2
+
+
 class View(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("B", ctypes.c_int32), ("stream", ctypes.c_void_p)]

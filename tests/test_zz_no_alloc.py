@@ -1,0 +1,83 @@
+"""ih_compute_noalloc (the allocation-free form of ih_compute, carries in the
+library's fixed per-GPU array) against ih_compute, through the C ABI: the
+same frames give the same bits, call after call, with a smaller frame after
+a larger one so that carries of the earlier call are still in the array.
+Both are also checked against the oracle (tolerance 0)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ihb():
+    from paper_1711_01919_amd import binding
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return binding
+
+
+def _frame(seed, H, W):
+    return np.random.default_rng(seed).integers(0, 256, size=(H, W), dtype=np.uint8)
+
+
+# (H, W, B) pairs: each second call is smaller than the first.
+PAIRS = [
+    ((1080, 1920, 64), (480, 640, 32)),        # the largest tile geometry first, then 640x480
+    ((480, 640, 32), (97, 203, 7)),            # ragged tail, B not a power of two
+    ((1080, 1920, 128), (33, 65, 256)),        # four bins per lane after two
+    ((2160, 3840, 64), (1, 1, 1)),             # near the array's limit, then a single pixel
+]
+
+
+@pytest.mark.parametrize("first,second", PAIRS, ids=[f"{a[0]}x{a[1]}x{a[2]}-then-{b[0]}x{b[1]}x{b[2]}"
+                                                     for a, b in PAIRS])
+def test_noalloc_matches_compute_twice(ihb, orc, first, second):
+    stream = torch.cuda.current_stream()
+    for seed, (H, W, B) in enumerate((first, second), start=11):
+        I = _frame(seed, H, W)
+        f = torch.from_numpy(I).cuda()
+        want = ihb.compute(f, B, stream=stream)
+        got = torch.full((H, W, B), 0xA5A5A5A5, dtype=torch.uint32, device="cuda")
+        ihb.compute_noalloc(f, B, got, stream=stream)
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), f"{H}x{W}x{B}: ih_compute_noalloc differs from ih_compute"
+        if H * W * B <= 64 << 20:
+            assert np.array_equal(got.cpu().numpy(), orc.integral_histogram(I, B)), f"{H}x{W}x{B} vs oracle"
+        else:
+            rows = [0, H // 2, H - 1]
+            g = got.cpu().numpy()
+            for y in rows:
+                assert np.array_equal(g[y], orc.row_by_definition(I, B, y)), f"{H}x{W}x{B} row {y}"
+
+
+def test_noalloc_rejects_frames_beyond_its_array(ihb):
+    """Frames whose carries exceed the array (1280x720 and 3840x2160 at
+    B=128): an error, nothing written."""
+    for H, W, B in ((720, 1280, 128), (2160, 3840, 128)):
+        f = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+        out = torch.full((4,), 7, dtype=torch.uint32, device="cuda")
+        st = ihb.lib.ih_compute_noalloc(ctypes.c_void_p(f.data_ptr()), H, W, B, ctypes.c_void_p(out.data_ptr()),
+                                        None)
+        assert st == 2                                          # IH_ERR_RANGE
+        torch.cuda.synchronize()
+        assert torch.equal(out, torch.full((4,), 7, dtype=torch.uint32, device="cuda"))
+
+
+def test_noalloc_ordered_calls_on_one_stream(ihb, orc):
+    """Several calls back to back on one stream without synchronising between
+    them (the array is reused in stream order), different frames and bins."""
+    stream = torch.cuda.current_stream()
+    shapes = [(480, 640, 32), (240, 320, 16), (480, 640, 64), (17, 1000, 3)]
+    frames = [_frame(40 + k, H, W) for k, (H, W, _) in enumerate(shapes)]
+    outs = []
+    for I, (H, W, B) in zip(frames, shapes):
+        o = torch.empty((H, W, B), dtype=torch.uint32, device="cuda")
+        ihb.compute_noalloc(torch.from_numpy(I).cuda(), B, o, stream=stream)
+        outs.append(o)
+    torch.cuda.synchronize()
+    for I, (H, W, B), o in zip(frames, shapes, outs):
+        assert np.array_equal(o.cpu().numpy(), orc.integral_histogram(I, B)), f"{H}x{W}x{B}"
