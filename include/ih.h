@@ -125,7 +125,7 @@ ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, 
  * Errors: as ih_compute, and IH_ERR_RANGE (nothing launched) when the
  * frame's carries exceed the array.  Every frame of at most 3840 x 2160
  * pixels fits at B <= 64; at larger B it depends on the tile ih_compute
- * picks (1920 x 1080 at B = 128 fits, 1280 x 720 at B = 128 does not).
+ * picks (1920 x 1080 at B = 128 fits, 1280 x 720 at B = 256 does not).
  */
 #define IH_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 ih_status ih_compute_noalloc(const uint8_t* frame, int32_t H, int32_t W, int32_t B, uint32_t* out,
@@ -203,7 +203,9 @@ typedef struct {
     int32_t use_graph;      /* 1: capture the launches in hipGraphs (default)        */
     int32_t tile_x, tile_y; /* both > 0: force this tile on every frame; tile_x is
                                32 for any B, 64 for B <= 128, 128 for B == 64;
-                               1 <= tile_y <= 65535 (else IH_ERR_INVALID_ARG)     */
+                               1 <= tile_y <= 65535 (else IH_ERR_INVALID_ARG).
+                               Bin-major frames keep 64-column tiles and take
+                               tile_y only                                        */
     int32_t nontemporal;    /* -1: as chosen; 0: regular stores; 1: non-temporal     */
     int64_t group_bytes;    /* > 0: pipelining.  Frames (in the order given) are
                                split into groups of about this many output bytes
@@ -218,8 +220,21 @@ typedef struct {
                                fused -- the count launch counts bands of K tile
                                bands and scans the carries itself, so the tile
                                pass follows it directly (K is clamped to a frame's
-                               band count; frames whose geometry cannot take it,
-                               and bin-major frames, keep reduce-then-scan)      */
+                               band count); -2: prefix counts -- each tile block
+                               of the count launch counts all rows above its
+                               band (the top carries, no scan) and the tile pass
+                               adds up the tile-column totals to its left (count
+                               work grows with the square of the band count).
+                               Frames whose geometry cannot take the schedule
+                               asked for, and bin-major frames, keep
+                               reduce-then-scan.                                 */
+    int32_t tile_branches;  /* 0: as chosen; 1: the tile-pass launches (one per
+                               compiled kernel variant) run one after another;
+                               2..4: they are spread over that many graph
+                               branches (streams) that fork after the carry
+                               phases and join before the launch ends, so one
+                               variant's tail overlaps another's start.  Not
+                               for pipelined plans (ignored there)            */
 } ih_batch_options;
 
 /* The schedule a plan chose for one frame. */
@@ -227,7 +242,7 @@ typedef struct {
     int32_t tile_x, tile_y;     /* tile: columns x rows                             */
     int32_t nontemporal;        /* 1: non-temporal output stores                    */
     int32_t carry_bands;        /* 0: reduce-then-scan; K >= 1: fused, K tile bands
-                                   per carry band                                   */
+                                   per carry band; -2: prefix counts                */
     int32_t group;              /* pipeline group of the frame (0 when one group)   */
 } ih_frame_schedule;
 

@@ -53,7 +53,7 @@ class FrameDesc(ctypes.Structure):
 class BatchOptions(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("group_bytes", ctypes.c_int64),
-                ("carry_bands", ctypes.c_int32)]
+                ("carry_bands", ctypes.c_int32), ("tile_branches", ctypes.c_int32)]
 
 
 class FrameSchedule(ctypes.Structure):
@@ -311,13 +311,16 @@ class BatchPlan:
     keeps references to them."""
 
     def __init__(self, frames, outs, bins, autotune=False, use_graph=True, tile=None,
-                 nontemporal=-1, stream=None, group_bytes=0, luts=None, binmajor=None, carry_bands=-1):
+                 nontemporal=-1, stream=None, group_bytes=0, luts=None, binmajor=None, carry_bands=-1,
+                 tile_branches=0):
         """group_bytes > 0 pipelines the plan in groups of about that many
         output bytes (see ih_batch_options in include/ih.h).  luts: None, or
         per frame None (uniform bins) or a 256-entry bin table.  binmajor:
         None, or per frame whether its output takes the (B, H, W) layout.
         carry_bands: -1 as chosen, 0 reduce-then-scan, K >= 1 the fused carry
-        schedule with K tile bands per carry band."""
+        schedule with K tile bands per carry band, -2 prefix counts.
+        tile_branches: 0 as chosen, 1 tile-pass launches one after another,
+        2..4 spread over that many graph branches."""
         if not (len(frames) == len(outs) == len(bins)) or len(frames) == 0:
             raise ValueError("frames, outs and bins must be equally long and non-empty")
         tables = [None] * len(frames) if luts is None else [
@@ -338,7 +341,7 @@ class BatchPlan:
                                  None if tables[k] is None else tables[k].ctypes.data, 1 if layouts[k] else 0)
         tx, ty = tile if tile else (0, 0)
         opt = BatchOptions(1 if autotune else 0, 1 if use_graph else 0, tx, ty, int(nontemporal),
-                           int(group_bytes), int(carry_bands))
+                           int(group_bytes), int(carry_bands), int(tile_branches))
         h = ctypes.c_void_p()
         _check(lib.ih_batch_plan_create(descs, len(frames), ctypes.byref(opt), _stream_handle(stream),
                                         ctypes.byref(h)), "ih_batch_plan_create")

@@ -25,6 +25,12 @@ namespace {
 using ih::fail;
 using ih::hip_fail;
 
+// Graph branches of the tile pass: at most kMaxTileBranches (the hardware
+// queues a process gets by default), kDefaultTileBranches when the caller
+// leaves the choice.
+constexpr int32_t kMaxTileBranches = 4;
+constexpr int32_t kDefaultTileBranches = 1;
+
 }  // namespace
 
 // A pipeline group: consecutive frames of the plan with their own launch
@@ -57,15 +63,55 @@ struct ih_batch_plan {
     hipStream_t stream = nullptr;         // creation stream (clears scratch, runs the autotuner)
     hipEvent_t ev_done = nullptr;         // recorded after each launch; destroy waits for it
     bool launched = false;
+    // Tile-pass launches spread over graph branches (one group only): the
+    // branch streams, the fork and join events, and (launch index, branch)
+    // in enqueue order.
+    int32_t tile_branches = 1;
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> ev_branch;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<std::pair<size_t, int>> tile_order;
 };
 
 namespace {
 
 // Enqueue the launches of the given phase (-1: all), in order.  Not for
-// pipelined plans.
+// pipelined plans.  With tile branches, the tile-pass launches fork from s
+// after the carry phases, run on the branch streams (each launch writes
+// frames of its own, so they are independent) and join s again.
 hipError_t enqueue(const ih_batch_plan* p, int phase, hipStream_t s)
 {
-    return ih::enqueue_batch(p->image, p->d_image, phase, s);
+    if (p->branch.empty() || (phase != -1 && phase != 2)) return ih::enqueue_batch(p->image, p->d_image, phase, s);
+    hipError_t e = hipSuccess;
+    for (int ph = 0; e == hipSuccess && phase == -1 && ph < 2; ++ph) e = ih::enqueue_batch(p->image, p->d_image, ph, s);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_fork, s);
+    for (size_t b = 0; e == hipSuccess && b < p->branch.size(); ++b) e = hipStreamWaitEvent(p->branch[b], p->ev_fork, 0);
+    for (size_t q = 0; e == hipSuccess && q < p->tile_order.size(); ++q)
+        e = ih::enqueue_launch(p->image, p->d_image, p->tile_order[q].first, p->branch[p->tile_order[q].second]);
+    for (size_t b = 0; e == hipSuccess && b < p->branch.size(); ++b) {
+        e = hipEventRecord(p->ev_branch[b], p->branch[b]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_branch[b], 0);
+    }
+    return e;
+}
+
+// Tile-pass launches over the branches: largest output first, each to the
+// branch with the least output so far.
+void assign_branches(ih_batch_plan* p)
+{
+    std::vector<size_t> tiles;
+    for (size_t i = 0; i < p->image.launches.size(); ++i)
+        if (ih::phase_of(p->image.launches[i]) == 2) tiles.push_back(i);
+    std::stable_sort(tiles.begin(), tiles.end(), [&](size_t a, size_t b) {
+        return p->image.launches[a].out_bytes > p->image.launches[b].out_bytes;
+    });
+    std::vector<int64_t> load(p->branch.size(), 0);
+    p->tile_order.clear();
+    for (size_t i : tiles) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += p->image.launches[i].out_bytes;
+        p->tile_order.emplace_back(i, b);
+    }
 }
 
 // The pipelined form.  Group g's carry phases run on the side stream after
@@ -109,6 +155,9 @@ void free_plan(ih_batch_plan* p)
     if (p->ev_start) (void)hipEventDestroy(p->ev_start);
     if (p->ev_done) (void)hipEventDestroy(p->ev_done);
     if (p->side) (void)hipStreamDestroy(p->side);
+    for (hipEvent_t e : p->ev_branch) (void)hipEventDestroy(e);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    for (hipStream_t b : p->branch) (void)hipStreamDestroy(b);
     if (p->d_image) (void)hipFree(p->d_image);
     if (p->d_luts) (void)hipFree(p->d_luts);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
@@ -180,6 +229,20 @@ ih_status build_plan(ih_batch_plan* p)
         }
         e = hipMemcpy(p->d_image, p->image.host.data(), p->image.bytes(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "upload batch tables");
+        int32_t tile_launches = 0;
+        for (const ih::BatchLaunch& l : p->image.launches) tile_launches += ih::phase_of(l) == 2;
+        const int32_t nb = std::min(p->tile_branches, tile_launches);
+        if (nb > 1) {
+            p->branch.assign((size_t)nb, nullptr);
+            p->ev_branch.assign((size_t)nb, nullptr);
+            for (int32_t b = 0; e == hipSuccess && b < nb; ++b) {
+                e = hipStreamCreateWithFlags(&p->branch[(size_t)b], hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_branch[(size_t)b], hipEventDisableTiming);
+            }
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "tile branches");
+            assign_branches(p);
+        }
         return IH_OK;
     }
     // Consecutive frames, group boundaries where the running output passes
@@ -276,10 +339,14 @@ TuneCache& tune_cache()
 
 const char* cache_path() { return std::getenv("IH_AUTOTUNE_CACHE"); }
 
-// The cache file holds one line per class: "gfx950/2 H W B NB TX TY NT K"
+// The cache file holds one line per class: "gfx950/3 H W B NB TX TY NT K"
 // (K: tile bands per carry band of the fused schedule, 0 for
-// reduce-then-scan).  Lines of any other tag are skipped.
-constexpr const char* kCacheTag = "gfx950/2";
+// reduce-then-scan, -2 for prefix counts).  Lines of any other tag are
+// skipped.
+constexpr const char* kCacheTag = "gfx950/3";
+constexpr int32_t kPrefixCode = -2;       // the prefix-count schedule in the cache and the ABI
+
+int32_t schedule_code(const ih::TileChoice& t) { return t.prefix ? kPrefixCode : t.K; }
 
 void load_cache(TuneCache& c)
 {
@@ -294,10 +361,11 @@ void load_cache(TuneCache& c)
         std::string tag;
         int H, W, B, NB, TX, TY, NT, K;
         if (!(ls >> tag >> H >> W >> B >> NB >> TX >> TY >> NT >> K) || tag != kCacheTag) continue;
-        if (H < 1 || W < 1 || B < 1 || B > 256 || K < 0) continue;
-        ih::TileChoice t{TX, TY, NT != 0, K};
+        if (H < 1 || W < 1 || B < 1 || B > 256 || (K < 0 && K != kPrefixCode)) continue;
+        ih::TileChoice t{TX, TY, NT != 0, K > 0 ? K : 0, K == kPrefixCode};
         if (!ih::tile_supported(B, t)) continue;
-        if (K && !ih::fused_supported(ih::make_geom(H, W, B, t))) continue;
+        if (t.K && !ih::fused_supported(ih::make_geom(H, W, B, t))) continue;
+        if (t.prefix && !ih::prefix_supported(ih::make_geom(H, W, B, t))) continue;
         c.best[TuneKey{H, W, B, NB}] = t;
     }
 }
@@ -309,29 +377,40 @@ void save_cache(TuneCache& c)
     std::ofstream out(path);
     for (auto& kv : c.best)
         out << kCacheTag << ' ' << kv.first.H << ' ' << kv.first.W << ' ' << kv.first.B << ' ' << kv.first.nb << ' '
-            << kv.second.TX << ' ' << kv.second.TY << ' ' << (kv.second.nontemporal ? 1 : 0) << ' ' << kv.second.K
-            << '\n';
+            << kv.second.TX << ' ' << kv.second.TY << ' ' << (kv.second.nontemporal ? 1 : 0) << ' '
+            << schedule_code(kv.second) << '\n';
+}
+
+bool same_choice(const ih::TileChoice& a, const ih::TileChoice& b)
+{
+    return a.TX == b.TX && a.TY == b.TY && a.nontemporal == b.nontemporal && a.K == b.K && a.prefix == b.prefix;
 }
 
 // Candidates of a class of H x W frames: every supported tile width, band
-// height and store flavour, each under both carry schedules (reduce-then-scan,
-// and fused with carry bands of ceil(nTY / 16) tile bands).
+// height and store flavour, each under the three carry schedules
+// (reduce-then-scan; fused with carry bands of ceil(nTY / 16) tile bands;
+// prefix counts, for frames of at most kMaxPrefixBands bands, where its
+// quadratic count work stays small).
 std::vector<ih::TileChoice> candidates(int32_t H, int32_t W, int32_t B)
 {
     std::vector<ih::TileChoice> c;
     for (int tx : {32, 64, 128})
-        for (int ty : {16, 32, 64, 128, 256})
+        for (int ty : {8, 16, 32, 64, 128, 256})
             for (bool nt : {false, true})
-                for (int fused : {0, 1}) {
+                for (int sched : {0, 1, 2}) {
                     ih::TileChoice t{tx, ih::even_band_height(H, ty), nt, 0};
                     if (!ih::tile_supported(B, t)) continue;
-                    if (fused) {
-                        t.K = ih::fused_bands((H + t.TY - 1) / t.TY, 16);
+                    const int32_t nTY = (H + t.TY - 1) / t.TY;
+                    if (sched == 1) {
+                        t.K = ih::fused_bands(nTY, 16);
                         if (!ih::fused_supported(ih::make_geom(H, W, B, t))) continue;
                     }
+                    if (sched == 2) {
+                        t.prefix = true;
+                        if (nTY > ih::kMaxPrefixBands || !ih::prefix_supported(ih::make_geom(H, W, B, t))) continue;
+                    }
                     bool dup = false;
-                    for (const ih::TileChoice& u : c)
-                        dup |= u.TX == t.TX && u.TY == t.TY && u.nontemporal == t.nontemporal && u.K == t.K;
+                    for (const ih::TileChoice& u : c) dup |= same_choice(u, t);
                     if (!dup) c.push_back(t);
                 }
     return c;
@@ -367,33 +446,28 @@ ih::TileChoice batch_default_tile(const std::vector<ih_frame_desc>& descs, int32
     return t;
 }
 
-// Bin-major frames of a batch (64-column tiles, the bin-major pass): the
-// tallest power-of-two band, up to 512 rows, that still gives the batch's
-// bin-major frames kMinBmItems work items together; each frame's bands are
-// then made even.  The single-frame item target taken over the whole batch
-// measured best (64 x 1080p B=64: 8.00 ms at 360-row bands against 8.44 ms
-// for a 65536-item target and 9.52 ms with each frame's own single-frame
-// tiles; 8 frames: 1.06 against 1.17 and 1.79 ms).
-constexpr int64_t kMinBmItems = 3840;
-
-void binmajor_batch_tiles(ih_batch_plan* p)
+// Bin-major frames of a batch: tiles chosen over all of them together
+// (binmajor_tiles); a forced tile height (forced_ty > 0) is taken as it is,
+// with four columns per lane.
+void binmajor_batch_tiles(ih_batch_plan* p, int32_t forced_ty)
 {
     std::vector<size_t> ks;
+    std::vector<ih::BinmajorShape> shapes;
     for (size_t k = 0; k < p->descs.size(); ++k)
-        if (p->descs[k].binmajor) ks.push_back(k);
-    if (ks.empty()) return;
-    auto items_of = [&](int ty) {
-        int64_t it = 0;
-        for (size_t k : ks) {
-            const ih_frame_desc& d = p->descs[k];
-            const ih::Geom g = ih::make_geom(d.H, d.W, d.B, ih::TileChoice{64, ty, false});
-            it += ih::tile_bm_items(g);
+        if (p->descs[k].binmajor) {
+            ks.push_back(k);
+            shapes.push_back(ih::BinmajorShape{p->descs[k].H, p->descs[k].W, p->descs[k].B});
         }
-        return it;
-    };
-    int ty = 512;
-    while (ty > 8 && items_of(ty) < kMinBmItems) ty /= 2;
-    for (size_t k : ks) p->tiles[k] = ih::TileChoice{64, ih::even_band_height(p->descs[k].H, ty), false};
+    if (ks.empty()) return;
+    std::vector<ih::TileChoice> t(ks.size());
+    ih::binmajor_tiles(shapes.data(), shapes.size(), t.data());
+    for (size_t q = 0; q < ks.size(); ++q) {
+        if (forced_ty > 0) {
+            t[q].TY = forced_ty;
+            t[q].bm_cpl = 4;
+        }
+        p->tiles[ks[q]] = t[q];
+    }
 }
 
 // Time one candidate on the frames of a class (all phases, no graph).
@@ -458,7 +532,7 @@ ih_status autotune(ih_batch_plan* p, hipStream_t s)
             float best_ms = 1e30f;
             if (ih_status st = time_candidate(descs, best, s, &best_ms)) return st;
             for (const ih::TileChoice& t : candidates(kv.first.H, kv.first.W, kv.first.B)) {
-                if (t.TX == best.TX && t.TY == best.TY && t.nontemporal == best.nontemporal && t.K == best.K) continue;
+                if (same_choice(t, best)) continue;
                 float ms = 0.f;
                 if (ih_status st = time_candidate(descs, t, s, &ms)) return st;
                 if (ms < 0.98f * best_ms) { best_ms = ms; best = t; }
@@ -483,10 +557,13 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     *plan = nullptr;
     if (n == 0 || !frames) return fail(IH_ERR_INVALID_ARG, "need at least one frame");
     if (n > (1u << 20)) return fail(IH_ERR_RANGE, "too many frames (%zu)", n);
-    ih_batch_options o{0, 1, 0, 0, -1, 0, -1};
+    ih_batch_options o{0, 1, 0, 0, -1, 0, -1, 0};
     if (opt) o = *opt;
+    if (o.tile_branches < 0 || o.tile_branches > kMaxTileBranches)
+        return fail(IH_ERR_INVALID_ARG, "tile_branches=%d must be in [0, %d]", o.tile_branches, kMaxTileBranches);
     const bool forced = o.tile_x > 0 || o.tile_y > 0;
-    if (o.carry_bands < -1) return fail(IH_ERR_INVALID_ARG, "carry_bands=%d must be >= -1", o.carry_bands);
+    if (o.carry_bands < kPrefixCode)
+        return fail(IH_ERR_INVALID_ARG, "carry_bands=%d must be >= %d", o.carry_bands, kPrefixCode);
     for (size_t k = 0; k < n; ++k) {
         const ih_frame_desc& d = frames[k];
         if (!d.frame || !d.out) return fail(IH_ERR_INVALID_ARG, "frame %zu: null pointer", k);
@@ -494,6 +571,8 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
         if (reinterpret_cast<uintptr_t>(d.out) & 3u) return fail(IH_ERR_INVALID_ARG, "frame %zu: out misaligned", k);
         if (forced && !d.binmajor && !ih::tile_supported(d.B, ih::TileChoice{o.tile_x, o.tile_y, false}))
             return fail(IH_ERR_INVALID_ARG, "tile %dx%d not supported for B=%d", o.tile_x, o.tile_y, d.B);
+        if (forced && d.binmajor && (o.tile_y < 1 || o.tile_y > 65535))
+            return fail(IH_ERR_INVALID_ARG, "frame %zu: tile_y=%d must be in [1, 65535]", k, o.tile_y);
         if (d.binmajor != 0 && d.binmajor != 1)
             return fail(IH_ERR_INVALID_ARG, "frame %zu: binmajor must be 0 or 1", k);
         if (d.binmajor && d.lut)
@@ -519,6 +598,7 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     }
     p->use_graph = o.use_graph != 0;
     p->group_bytes = o.group_bytes;
+    p->tile_branches = o.tile_branches > 0 ? o.tile_branches : kDefaultTileBranches;
     p->tiles.resize(n);
     int64_t total_out = 0;
     for (size_t k = 0; k < n; ++k) total_out += (int64_t)frames[k].H * frames[k].W * frames[k].B * 4;
@@ -547,13 +627,20 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
     }
     if (st == IH_OK && o.nontemporal >= 0)
         for (auto& t : p->tiles) t.nontemporal = o.nontemporal != 0;
-    // A forced carry schedule: reduce-then-scan (0), or fused with that many
-    // tile bands per carry band, clamped to each frame's band count and kept
-    // only where the frame's geometry supports it.
-    for (size_t k = 0; st == IH_OK && o.carry_bands >= 0 && k < n; ++k) {
+    // A forced carry schedule: reduce-then-scan (0), prefix counts (-2), or
+    // fused with that many tile bands per carry band, clamped to each frame's
+    // band count; each kept only where the frame's geometry supports it.
+    for (size_t k = 0; st == IH_OK && o.carry_bands != -1 && k < n; ++k) {
         ih::TileChoice& t = p->tiles[k];
         t.K = 0;
+        t.prefix = false;
         if (o.carry_bands == 0) continue;
+        if (o.carry_bands == kPrefixCode) {
+            ih::TileChoice q = t;
+            q.prefix = true;
+            if (ih::prefix_supported(ih::make_geom(frames[k].H, frames[k].W, frames[k].B, q))) t = q;
+            continue;
+        }
         const int32_t nTY = (frames[k].H + t.TY - 1) / t.TY;
         ih::TileChoice f = t;
         f.K = std::min(o.carry_bands, nTY);
@@ -567,9 +654,10 @@ ih_status ih_batch_plan_create(const ih_frame_desc* frames, size_t n, const ih_b
         p->tiles[k].nontemporal = false;
         p->descs[k].lut = nullptr;
     }
-    // Bin-major frames: 64-column tiles (what the bin-major pass is written
-    // for), bands chosen over the batch's bin-major frames together.
-    if (st == IH_OK) binmajor_batch_tiles(p);
+    // Bin-major frames: 64-column carry tiles (what the bin-major pass is
+    // written for), bands chosen over the batch's bin-major frames together
+    // unless a tile is forced (its height is kept).
+    if (st == IH_OK) binmajor_batch_tiles(p, forced ? o.tile_y : 0);
     if (st == IH_OK) st = build_plan(p);
     if (st == IH_OK && p->use_graph) {
         st = capture(p, -1, &p->exec_all);
@@ -668,7 +756,7 @@ ih_status ih_batch_plan_frame_schedule(const ih_batch_plan* p, size_t k, ih_fram
     sched->tile_x = p->tiles[k].TX;
     sched->tile_y = p->tiles[k].TY;
     sched->nontemporal = p->tiles[k].nontemporal ? 1 : 0;
-    sched->carry_bands = p->tiles[k].K;
+    sched->carry_bands = schedule_code(p->tiles[k]);
     int32_t group = 0;
     for (size_t g = 0, first = 0; g < p->groups.size(); ++g) {
         const size_t frames_in = p->groups[g].frames;

@@ -37,6 +37,11 @@ bool fused_supported(const Geom& g)
     return g.K >= 1 && (int64_t)g.nTX + g.nS <= kCounterWords && (int64_t)g.K * g.TY <= 65535;
 }
 
+bool prefix_supported(const Geom& g)
+{
+    return g.PC == 1 && g.K == 0 && g.H <= 65536 && g.nTX <= kMaxPrefixTileColumns;
+}
+
 int32_t fused_bands(int32_t nTY, int32_t max_bands)
 {
     return (nTY + max_bands - 1) / max_bands;
@@ -57,7 +62,9 @@ Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t)
     g.L = (B + g.BPL - 1) / g.BPL;
     g.S = kWave / g.L;
     g.nJG = (g.nTX + g.S - 1) / g.S;
-    g.K = t.K > 0 ? t.K : 0;
+    g.PC = t.prefix ? 1 : 0;
+    g.CPL = t.bm_cpl;
+    g.K = t.K > 0 && !t.prefix ? t.K : 0;
     g.nS = g.K ? (g.nTY + g.K - 1) / g.K : 0;
     return g;
 }
@@ -92,28 +99,55 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B)
     int TY = 512;
     while (TY > 16 && (int64_t)((H + TY - 1) / TY) * g0.nJG < kMinWaves) TY /= 2;
     t.TY = TY;
-    // Small frames (too few waves even at 16 rows): narrower and shorter
-    // tiles for parallelism; their carries stay in cache.
+    // Small frames (too few waves even at 16 rows): 32-column tiles for
+    // parallelism and the prefix-count schedule (two launches, no scans;
+    // 640 x 480 B=32: 25.0 against 29.0 us per frame under reduce-then-scan
+    // with 8-row bands).  Its count blocks read about bands / 2 frames' worth
+    // of pixels, so bands start at 8 rows and grow until there are at most
+    // kMaxPrefixBands of them and that stays within kPrefixCountPixels
+    // (1920 x 1080 B=16: 32-row bands, 70.6 us against 107 us at 8 rows and
+    // 150 us under reduce-then-scan).
     if ((int64_t)((H + TY - 1) / TY) * g0.nJG < kMinWaves) {
         t.TX = 32;
         t.TY = 8;
+        auto bands = [&](int ty) { return (H + ty - 1) / ty; };
+        while (t.TY < 64 && (bands(t.TY) > kMaxPrefixBands || (int64_t)H * W * bands(t.TY) / 2 > kPrefixCountPixels))
+            t.TY *= 2;
+        t.prefix = (H + t.TY - 1) / t.TY <= kMaxPrefixBands;
+        if (!t.prefix) t.TY = 8;
     }
     t.TY = even_band_height(H, t.TY);
+    if (t.prefix && !prefix_supported(make_geom(H, W, B, t))) t.prefix = false;
     return t;
+}
+
+void binmajor_tiles(const BinmajorShape* frames, size_t n, TileChoice* tiles)
+{
+    auto items = [&](int cpl, int ty) {
+        int64_t it = 0;
+        for (size_t k = 0; k < n; ++k) {
+            int bg = 16;
+            while (frames[k].B % bg != 0) bg >>= 1;
+            it += (int64_t)((frames[k].H + ty - 1) / ty) * bm_segments(frames[k].W, cpl) * (frames[k].B / bg);
+        }
+        return it;
+    };
+    const int cpl = items(4, 64) >= kBmItemsWide ? 4 : 1;
+    const int64_t target = cpl == 4 ? kBmItemsWide : kBmItemsNarrow;
+    int ty = 512;
+    while (ty > 8 && items(cpl, ty) < target) ty /= 2;
+    for (size_t k = 0; k < n; ++k) {
+        tiles[k] = TileChoice{64, even_band_height(frames[k].H, ty), false};
+        tiles[k].bm_cpl = cpl;
+    }
 }
 
 TileChoice binmajor_tile(int32_t H, int32_t W, int32_t B)
 {
-    int bg = 16;
-    while (B % bg != 0) bg >>= 1;
-    const int64_t cols = (W + 63) / 64, groups = B / bg;
-    int TY = 512;
-    // about 4000 work items: each writes 256 bytes into each of its bins'
-    // planes per row, a scattered pattern that needs more waves in flight
-    // than the H x W x B pass (measured: 8K B=16 at 30% of peak with ~1000
-    // items, 45% with ~4000)
-    while (TY > 8 && (int64_t)((H + TY - 1) / TY) * cols * groups < 3840) TY /= 2;
-    return TileChoice{64, even_band_height(H, TY), false};
+    const BinmajorShape f{H, W, B};
+    TileChoice t;
+    binmajor_tiles(&f, 1, &t);
+    return t;
 }
 
 int32_t interior_groups(const Geom& g, const uint8_t* frame, const uint32_t* out)

@@ -17,12 +17,17 @@ constexpr int kAggThreads = 256;     // threads per block of the per-tile count 
 // tile pass a wave covers S horizontally adjacent tiles ("segments"); inside a
 // segment, L lanes each own BPL consecutive bins.
 //
-// Carry schedule.  K == 0: reduce-then-scan -- the count launch counts each
-// tile, then two scan launches turn the counts into carries, then the tile
-// pass.  K >= 1: fused -- the count launch counts carry bands of K tile bands
-// (nS of them) and scans the carries itself (the last block to finish a tile
-// column scans that column, the last block to finish a carry band scans that
-// band), so the tile pass follows it directly.
+// Carry schedule.  K == 0, PC == 0: reduce-then-scan -- the count launch
+// counts each tile, then two scan launches turn the counts into carries, then
+// the tile pass.  K >= 1: fused -- the count launch counts carry bands of K
+// tile bands (nS of them) and scans the carries itself (the last block to
+// finish a tile column scans that column, the last block to finish a carry
+// band scans that band), so the tile pass follows it directly.  PC == 1:
+// prefix counts -- each tile block of the count launch counts every row above
+// its band, which gives the band's top carries with no scan, and their
+// tile-column totals; the tile pass sums the totals of the tile columns to
+// its left for its corner.  No scan launch and no inter-block communication;
+// the count work grows with the square of the band count.
 struct Geom {
     int32_t H, W, B;
     int32_t TX, TY;          // tile width (columns) and height (rows)
@@ -30,6 +35,8 @@ struct Geom {
     int32_t BPL, L, S;       // bins per lane, lanes per segment, segments per wave
     int32_t nJG;             // column groups (ceil(nTX / S)) = waves per tile row
     int32_t K, nS;           // fused schedule: tile bands per carry band, carry bands (0, 0: reduce-then-scan)
+    int32_t PC;              // 1: prefix-count schedule (then K == 0)
+    int32_t CPL;             // bin-major tile pass: columns per lane (1 or 4); 0 for H x W x B frames
 };
 
 // Arrival counters of the fused schedule sit in the first kCounterWords words
@@ -39,6 +46,17 @@ struct Geom {
 // zero again after every launch.
 constexpr int32_t kCounterWords = 4096;
 
+// Longest look-back of the prefix-count schedule's tile pass: the tile
+// columns to the left of a tile whose totals it adds up for its corner.
+constexpr int32_t kMaxPrefixTileColumns = 256;
+// Bands of the frames that take the prefix-count schedule by default (the
+// single-frame heuristic and the autotuner's candidates): its count work is
+// about bands / 2 reads of the frame.
+constexpr int32_t kMaxPrefixBands = 64;
+// Pixels the count blocks of a single frame may read under the prefix-count
+// schedule before the single-frame heuristic takes taller bands.
+constexpr int64_t kPrefixCountPixels = 40 << 20;
+
 // Scratch layout (uint32 words) for one frame:
 //   cnt    [kCounterWords]  fused schedule: arrivals per tile column (nTX), then
 //                           per carry band (nS)
@@ -47,6 +65,10 @@ constexpr int32_t kCounterWords = 4096;
 //   reduce-then-scan:
 //   colc   [nTY][W][B]      column counts per tile band, scanned to top carries
 //   corner [nTY][nTX][B]    per-tile totals, scanned to top-left corner counts
+//   prefix counts:
+//   colc   [nTY][W][B]      pixels of every row above band i, per column: the
+//                           band's top carries as they are
+//   corner [nTY][nTX][B]    their totals over each tile column
 //   fused (carry band I, snapshot s < K):
 //   colc   [nS][K][W][B]    s < K-1: column counts of the band's first s+1 tile
 //                           bands; s = K-1: of the whole band, scanned down the
@@ -91,13 +113,35 @@ struct TileChoice {
     int32_t TX, TY;
     bool nontemporal;
     int32_t K = 0;           // 0: reduce-then-scan; >= 1: fused with K tile bands per carry band
+    bool prefix = false;     // prefix-count schedule (K == 0)
+    int32_t bm_cpl = 0;      // bin-major frames: columns per lane of the tile pass (1 or 4)
 };
 
 int bins_per_lane(int B);
 Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t);
 TileChoice default_tile(int32_t H, int32_t W, int32_t B);
-// Tile of the bin-major tile pass: 64 columns (one per lane), bands for about
-// 4000 work items of up to 16 bins.
+// Bin-major tile pass: a work item covers 64 * CPL columns (CPL per lane) of
+// a band for a group of up to 16 bins, on the carries of 64-column tiles.
+__host__ __device__ inline int32_t bm_segments(int32_t W, int32_t cpl)
+{
+    const int32_t cols = 64 * (cpl == 4 ? 4 : 1);
+    return (W + cols - 1) / cols;
+}
+__host__ __device__ inline int64_t tile_bm_items_of(const Geom& g, int32_t bg)
+{
+    return (int64_t)g.nTY * bm_segments(g.W, g.CPL) * (g.B / bg);
+}
+// Tiles of bin-major frames launched together (one frame for
+// ih_compute_binmajor, all of a plan's bin-major frames): four columns per
+// lane (1 KB store runs) and the tallest band, up to 512 rows, that leaves
+// kBmItemsWide items, when 64-row bands leave that many; otherwise one column
+// per lane and the tallest band that leaves kBmItemsNarrow items (small
+// frames need the items more than long runs).  Each frame's bands are then
+// made even.
+constexpr int64_t kBmItemsWide = 960;
+constexpr int64_t kBmItemsNarrow = 3840;
+struct BinmajorShape { int32_t H, W, B; };
+void binmajor_tiles(const BinmajorShape* frames, size_t n, TileChoice* tiles);
 TileChoice binmajor_tile(int32_t H, int32_t W, int32_t B);
 // The same number of bands as TY gives, made equally tall (the last band is
 // no shorter than the others by more than one row): a short last band makes
@@ -107,6 +151,10 @@ bool tile_supported(int32_t B, const TileChoice& t);
 // The fused schedule for this geometry: enough arrival counters, and carry
 // bands whose per-column counts fit 16 bits.
 bool fused_supported(const Geom& g);
+// The prefix-count schedule for this geometry: column counts of the rows
+// above a band fit the 16-bit LDS counters, and the tile pass's look-back
+// over the tile columns to its left stays short.
+bool prefix_supported(const Geom& g);
 // Carry bands of about `target` tile bands' worth for the fused schedule:
 // the K that leaves at most `max_bands` carry bands.
 int32_t fused_bands(int32_t nTY, int32_t max_bands);
@@ -171,8 +219,8 @@ hipError_t launch_tile_bm(const FrameArgs& f, hipStream_t stream);
 // width bg (a job per frame, `begin` its first item).
 int bm_group(int B);
 int64_t tile_bm_items(const Geom& g);
-hipError_t launch_tile_bm_batch(int bg, const FrameArgs* frames, const Job* jobs, int32_t njobs, int64_t nitems,
-                                hipStream_t stream);
+hipError_t launch_tile_bm_batch(int bg, int cpl, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                                int64_t nitems, hipStream_t stream);
 
 // Copy a host bin table (256 bytes, passed by value as a kernel argument) to
 // device memory dst (64 uint32, 4-byte aligned), in stream order.

@@ -187,22 +187,29 @@ __device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* l
     }
 }
 
+// Reduce-then-scan: the pixels of tile (i, j) itself.  Prefix counts: the
+// pixels of every row above band i in tile column j (rows [0, y0); counts
+// below 2^16 since H <= 65536), so colc holds the band's top carries as they
+// are and corner their tile-column totals.  The blocks of the lowest bands
+// count the most rows, so they come first in the launch.
 template <int TX>
 __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint32_t* colh, uint32_t* lutw)
 {
     const Geom& g = f.g;
     const int B = g.B;
-    const int i = (int)(tile / g.nTX);
-    const int j = (int)(tile - (int64_t)i * g.nTX);
+    const int r = (int)(tile / g.nTX);
+    const int j = (int)(tile - (int64_t)r * g.nTX);
+    const int i = g.PC ? g.nTY - 1 - r : r;
     const int x0 = j * TX, y0 = i * g.TY;
     const int tw = min(TX, g.W - x0);
-    const int th = min(g.TY, g.H - y0);
+    const int ya = g.PC ? 0 : y0;
+    const int yb = g.PC ? y0 : min(g.H, y0 + g.TY);
     const int tid = threadIdx.x;
 
     for (int e = tid; e < (TX * B + 1) / 2; e += kAggThreads) colh[e] = 0;
     stage_lut(f, lutw, tid, kAggThreads);
     __syncthreads();
-    count_rows<TX>(f, lutw, colh, y0, y0 + th, x0, tw);
+    count_rows<TX>(f, lutw, colh, ya, yb, x0, tw);
     __syncthreads();
     for (int e = tid; e < tw * B; e += kAggThreads)
         gmem(f.colc)[((size_t)i * g.W + x0) * B + e] = lds_get16(colh, (uint32_t)e);
@@ -635,14 +642,19 @@ void query_kernel(const uint32_t* __restrict__ ih_, int32_t H, int32_t W, int32_
 // ---------------------------------------------------------------------------
 // Phase 3, bin-major layout (the paper's b x h x w, Sec. 3.1 Fig. 2)
 // ---------------------------------------------------------------------------
-// Entry (x, y, b) at (b * H + y) * W + x.  One wave per (tile band, 64-column
-// segment, group of BG <= 16 bins, BG a power of two dividing B); lane l owns column
-// x0 + l.  For a row and a bin the in-row prefix across the segment is a
-// ballot of the lanes whose pixel falls in the bin and a count of the set
-// bits below each lane (mbcnt), plus the left carry of the row; the column
-// accumulators V[t] start from the corner and the lane prefix of the top
-// carries.  Stores are 256 contiguous bytes per bin and row.  The carry
-// phases are the same as for the H x W x B layout with 64-column tiles.
+// Entry (x, y, b) at (b * H + y) * W + x.  One wave per (tile band, segment of
+// 64 * CPL columns, group of BG <= 16 bins, BG a power of two dividing B);
+// lane l owns the CPL columns x0 + CPL l .. x0 + CPL l + CPL - 1, so each bin
+// plane gets 256 * CPL contiguous bytes per row from the wave (one store of
+// CPL dwords per lane).  CPL = 4 (1 KB runs) suits launches with many items;
+// CPL = 1 gives four times the items for small single frames.  For a row and
+// a bin, a lane counts the hits h among its CPL pixels; the exclusive prefix
+// of those counts across the lanes comes from one ballot per bit of h and
+// mbcnt; adding the row's left carry and the lane's own running hits gives
+// each column's in-row count.  The column accumulators V[t][c] start from the
+// corner and the prefix of the top carries along the segment.  The carry
+// phases are the same as for the H x W x B layout with 64-column tiles: a
+// segment J starts at carry tile j = CPL * J.
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, int lane)
 {
 #pragma unroll
@@ -653,47 +665,93 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, int lane)
     return v;
 }
 
-// Items of a frame: nTY * nTX * (B / BG), one wave each.
-template <int BG>
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <int CPL>
+__device__ __forceinline__ void store_run(IH_GLOBAL uint32_t* o, const uint32_t (&v)[CPL])
+{
+    if constexpr (CPL == 1) {
+        *o = v[0];
+    } else {
+        *reinterpret_cast<IH_GLOBAL u32x4*>(o) = u32x4{v[0], v[1], v[2], v[3]};
+    }
+}
+
+template <int BG, int CPL>
 __device__ __forceinline__ void tile_bm_body(const FrameArgs& f, int64_t item)
 {
+    static_assert(CPL == 1 || CPL == 4, "one or four columns per lane");
+    constexpr int kBits = CPL == 1 ? 1 : 3;                          // bits of a lane's hit count (<= CPL)
     const Geom& g = f.g;
     const int B = g.B, H = g.H, W = g.W;
     const int n_groups = B / BG;
+    const int nseg = bm_segments(W, CPL);
     const int lane = threadIdx.x % kWave;
     const int grp = (int)(item % n_groups);
-    const int64_t tile = item / n_groups;
-    const int i = (int)(tile / g.nTX), j = (int)(tile % g.nTX);
-    const int x0 = j * kWave, x = x0 + lane;
-    const bool valid = x < W;
+    const int64_t seg_item = item / n_groups;
+    const int i = (int)(seg_item / nseg), J = (int)(seg_item - (int64_t)i * nseg);
+    const int j = J * CPL;                               // carry tile of the segment's first column
+    const int xl = J * kWave * CPL + CPL * lane;          // the lane's first column
     const int y0 = i * g.TY, y1 = min(H, y0 + g.TY);
     const int b_lo = grp * BG;
+    const int nvalid = max(0, min(CPL, W - xl));         // the lane's columns inside the frame
+    // whole, aligned runs: one load of the lane's pixels, one store per bin and row
+    const bool vec = nvalid == CPL && (W % CPL) == 0 && ((reinterpret_cast<uintptr_t>(f.frame) & (CPL - 1)) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(f.out) & (4 * CPL - 1)) == 0);
 
-    uint32_t V[BG];
+    uint32_t V[BG][CPL];
     {
         const IH_GLOBAL uint32_t* cp = gmem(f.corner) + ((size_t)i * g.nTX + j) * B + b_lo;
-        const IH_GLOBAL uint32_t* tp = gmem(f.colc) + ((size_t)i * W + x) * B + b_lo;
+        const IH_GLOBAL uint32_t* tp = gmem(f.colc) + ((size_t)i * W + xl) * B + b_lo;
         const uint32_t corner = lane < BG ? cp[lane] : 0u;     // lane t: corner of bin b_lo + t
 #pragma unroll
         for (int t = 0; t < BG; ++t) {
-            const uint32_t c = valid ? tp[t] : 0u;
-            V[t] = (uint32_t)__builtin_amdgcn_readlane((int)corner, t) + wave_inclusive_sum(c, lane);
+            uint32_t top[CPL], sum = 0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                top[c] = c < nvalid ? tp[(size_t)c * B + t] : 0u;
+                sum += top[c];
+            }
+            uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)corner, t) + wave_inclusive_sum(sum, lane) - sum;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                run += top[c];
+                V[t][c] = run;
+            }
         }
     }
     const IH_GLOBAL uint8_t* frame = gmem(f.frame);
     const IH_GLOBAL uint32_t* rowc = gmem(f.rowc) + (size_t)j * H * B + b_lo;
     IH_GLOBAL uint32_t* out = gmem(f.out);
     const size_t plane = (size_t)H * W;
-    // Pixels (binned) and left carries come 8 rows at a time, a chunk ahead:
-    // lane t holds the carry of bin b_lo + t; rows past the band are clamped.
+    // Pixels (CPL per lane, packed) and left carries come 8 rows at a time, a
+    // chunk ahead: lane t holds the carry of bin b_lo + t; rows past the band
+    // are clamped.
     constexpr int CH = 8;
     uint32_t cq[CH], cc[CH], nq[CH], nc[CH];
     auto load_chunk = [&](int yc, uint32_t (&q)[CH], uint32_t (&c)[CH]) {
 #pragma unroll
         for (int r = 0; r < CH; ++r) {
             const int row = min(yc + r, y1 - 1);
-            const uint32_t v = valid ? frame[(size_t)row * W + x] : 0u;
-            q[r] = valid ? (v * (uint32_t)B) >> 8 : 0xFFFFu;
+            const IH_GLOBAL uint8_t* p = frame + (size_t)row * W + xl;
+            if constexpr (CPL == 4) {
+                if (vec) {
+                    q[r] = *reinterpret_cast<const IH_GLOBAL uint32_t*>(p);
+                } else {
+                    uint32_t w = 0;
+                    for (int k = 0; k < nvalid; ++k) w |= (uint32_t)p[k] << (8 * k);
+                    q[r] = w;
+                }
+            } else {
+                uint32_t w = 0;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k)
+                    if (k < nvalid) w |= (uint32_t)p[k] << (8 * k);
+                q[r] = w;
+            }
             c[r] = lane < BG ? rowc[(size_t)row * B + lane] : 0u;
         }
     };
@@ -705,15 +763,39 @@ __device__ __forceinline__ void tile_bm_body(const FrameArgs& f, int64_t item)
         for (int r = 0; r < CH; ++r) {
             const int y = yc + r;
             if (y < y1) {
-                IH_GLOBAL uint32_t* orow = out + (size_t)b_lo * plane + (size_t)y * W + x;
+                // bins of the lane's pixels; 256 (no bin) past the frame
+                uint32_t q[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    q[c] = c < nvalid ? (((cq[r] >> (8 * c)) & 0xFFu) * (uint32_t)B) >> 8 : 256u;
+                IH_GLOBAL uint32_t* orow = out + (size_t)b_lo * plane + (size_t)y * W + xl;
 #pragma unroll
                 for (int t = 0; t < BG; ++t) {
-                    const bool hit = cq[r] == (uint32_t)(b_lo + t);
-                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-                    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    V[t] += (uint32_t)__builtin_amdgcn_readlane((int)cc[r], t) + below + (hit ? 1u : 0u);
-                    if (valid) orow[(size_t)t * plane] = V[t];
+                    const uint32_t b = (uint32_t)(b_lo + t);
+                    uint32_t h[CPL], s = 0;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        h[c] = q[c] == b ? 1u : 0u;
+                        s += h[c];
+                    }
+                    uint32_t below = 0;
+#pragma unroll
+                    for (int k = 0; k < kBits; ++k)
+                        below += lanes_below(__builtin_amdgcn_ballot_w64(((s >> k) & 1u) != 0)) << k;
+                    uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)cc[r], t) + below;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        run += h[c];
+                        V[t][c] += run;
+                    }
+                    IH_GLOBAL uint32_t* o = orow + (size_t)t * plane;
+                    if (vec) {
+                        store_run<CPL>(o, V[t]);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c)
+                            if (c < nvalid) o[c] = V[t][c];
+                    }
                 }
             }
         }
@@ -727,18 +809,19 @@ __device__ __forceinline__ void tile_bm_body(const FrameArgs& f, int64_t item)
     }
 }
 
-template <int BG>
+template <int BG, int CPL>
 __global__ __launch_bounds__(kWave * kWavesPerBlock)
 void tile_bm_kernel(FrameArgs f)
 {
     const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
-    if (item >= (int64_t)f.g.nTY * f.g.nTX * (f.g.B / BG)) return;     // whole wave leaves together
-    tile_bm_body<BG>(f, item);
+    if (item >= tile_bm_items_of(f.g, BG)) return;                     // whole wave leaves together
+    tile_bm_body<BG, CPL>(f, item);
 }
 
-// Many bin-major frames with the same bin group BG: one wave per item over
-// the job table (a job per frame, `begin` its first item).
-template <int BG>
+// Many bin-major frames with the same bin group BG and columns per lane CPL:
+// one wave per item over the job table (a job per frame, `begin` its first
+// item).
+template <int BG, int CPL>
 __global__ __launch_bounds__(kWave * kWavesPerBlock)
 void tile_bm_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs,
                           int64_t nitems)
@@ -747,7 +830,7 @@ void tile_bm_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __res
     if (item >= nitems) return;                                        // whole wave leaves together
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, item));
     const FrameArgs f = cload(frames, jb.frame);
-    tile_bm_body<BG>(f, item - jb.begin);
+    tile_bm_body<BG, CPL>(f, item - jb.begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -871,7 +954,7 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
         break;
     }
     case Phase::kScan:
-        if (g.K) break;                 // fused: the count launch scanned the carries
+        if (g.K || g.PC) break;         // fused or prefix counts: no scan launch
         if (scan_parts(g.nTY) == 1)
             hipLaunchKernelGGL(scan_a_kernel<1>, dim3((unsigned)scan_a_blocks(g)), dim3(kScanThreads), 0, stream, f);
         else
@@ -982,38 +1065,51 @@ int bm_group(int B)
     return bg;
 }
 
-hipError_t launch_tile_bm(const FrameArgs& f, hipStream_t stream)
+template <int CPL>
+static void launch_bm_single(int bg, const FrameArgs& f, unsigned blocks, hipStream_t stream)
 {
-    const Geom& g = f.g;
-    const int bg = bm_group(g.B);
-    const int64_t items = (int64_t)g.nTY * g.nTX * (g.B / bg);
-    const unsigned blocks = (unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock);
     const dim3 grid(blocks), block(kWave * kWavesPerBlock);
     switch (bg) {
-    case 16: hipLaunchKernelGGL(tile_bm_kernel<16>, grid, block, 0, stream, f); break;
-    case 8: hipLaunchKernelGGL(tile_bm_kernel<8>, grid, block, 0, stream, f); break;
-    case 4: hipLaunchKernelGGL(tile_bm_kernel<4>, grid, block, 0, stream, f); break;
-    case 2: hipLaunchKernelGGL(tile_bm_kernel<2>, grid, block, 0, stream, f); break;
-    default: hipLaunchKernelGGL(tile_bm_kernel<1>, grid, block, 0, stream, f); break;
+    case 16: hipLaunchKernelGGL((tile_bm_kernel<16, CPL>), grid, block, 0, stream, f); break;
+    case 8: hipLaunchKernelGGL((tile_bm_kernel<8, CPL>), grid, block, 0, stream, f); break;
+    case 4: hipLaunchKernelGGL((tile_bm_kernel<4, CPL>), grid, block, 0, stream, f); break;
+    case 2: hipLaunchKernelGGL((tile_bm_kernel<2, CPL>), grid, block, 0, stream, f); break;
+    default: hipLaunchKernelGGL((tile_bm_kernel<1, CPL>), grid, block, 0, stream, f); break;
     }
+}
+
+hipError_t launch_tile_bm(const FrameArgs& f, hipStream_t stream)
+{
+    const int64_t items = tile_bm_items(f.g);
+    const unsigned blocks = (unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (f.g.CPL == 4) launch_bm_single<4>(bm_group(f.g.B), f, blocks, stream);
+    else launch_bm_single<1>(bm_group(f.g.B), f, blocks, stream);
     return hipGetLastError();
 }
 
-int64_t tile_bm_items(const Geom& g) { return (int64_t)g.nTY * g.nTX * (g.B / bm_group(g.B)); }
+int64_t tile_bm_items(const Geom& g) { return tile_bm_items_of(g, bm_group(g.B)); }
 
-hipError_t launch_tile_bm_batch(int bg, const FrameArgs* frames, const Job* jobs, int32_t njobs, int64_t nitems,
-                                hipStream_t stream)
+template <int CPL>
+static void launch_bm_batch(int bg, const FrameArgs* frames, const Job* jobs, int32_t njobs, int64_t nitems,
+                            hipStream_t stream)
 {
-    if (nitems <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((nitems + kWavesPerBlock - 1) / kWavesPerBlock);
     const dim3 grid(blocks), block(kWave * kWavesPerBlock);
     switch (bg) {
-    case 16: hipLaunchKernelGGL(tile_bm_batch_kernel<16>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
-    case 8: hipLaunchKernelGGL(tile_bm_batch_kernel<8>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
-    case 4: hipLaunchKernelGGL(tile_bm_batch_kernel<4>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
-    case 2: hipLaunchKernelGGL(tile_bm_batch_kernel<2>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
-    default: hipLaunchKernelGGL(tile_bm_batch_kernel<1>, grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    case 16: hipLaunchKernelGGL((tile_bm_batch_kernel<16, CPL>), grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    case 8: hipLaunchKernelGGL((tile_bm_batch_kernel<8, CPL>), grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    case 4: hipLaunchKernelGGL((tile_bm_batch_kernel<4, CPL>), grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    case 2: hipLaunchKernelGGL((tile_bm_batch_kernel<2, CPL>), grid, block, 0, stream, frames, jobs, njobs, nitems); break;
+    default: hipLaunchKernelGGL((tile_bm_batch_kernel<1, CPL>), grid, block, 0, stream, frames, jobs, njobs, nitems); break;
     }
+}
+
+hipError_t launch_tile_bm_batch(int bg, int cpl, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                                int64_t nitems, hipStream_t stream)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (cpl == 4) launch_bm_batch<4>(bg, frames, jobs, njobs, nitems, stream);
+    else launch_bm_batch<1>(bg, frames, jobs, njobs, nitems, stream);
     return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ size_t frame_scratch_words(const Geom& g) { return align_up(scratch_layout(g).wo
 
 size_t batch_image_bound(size_t n)
 {
-    const size_t launches = 3 + 4 + 2 * n + 5;
+    const size_t launches = 3 + 4 + 2 * n + 10;
     return align_up(n * sizeof(FrameArgs), 256) + launches * 256 + 7 * n * sizeof(Job) + 256;
 }
 
@@ -98,7 +98,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         int64_t begin = 0;
         for (size_t k = 0; k < n; ++k) {
             const Geom& g = frames[k].g;
-            if (g.K) continue;          // fused: carries scanned in the count launch
+            if (g.K || g.PC) continue;  // fused or prefix counts: carries ready after the count launch
             if (scan_parts(kind == BatchLaunch::kScanA ? g.nTY : g.nTX) != parts) continue;
             const int64_t nb = kind == BatchLaunch::kScanA ? scan_a_blocks(g) : scan_b_blocks(g);
             if (nb == 0) continue;
@@ -115,7 +115,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         tables.push_back(std::move(jobs));
     }
     std::map<TileVariant, std::vector<Job>> byv;
-    std::map<TileVariant, int64_t> items;
+    std::map<TileVariant, int64_t> items, obytes;
     for (size_t k = 0; k < n; ++k) {
         if (binmajor && (*binmajor)[k]) continue;
         const Geom& g = frames[k].g;
@@ -127,6 +127,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
             int64_t& b = items[v];
             byv[v].push_back(Job{b, (int32_t)k, parts[q][0], parts[q][1], 0});
             b += (int64_t)g.nTY * parts[q][1];
+            obytes[v] += (int64_t)g.H * g.W * g.B * 4 * parts[q][1] / g.nJG;
         }
     }
     for (auto& kv : byv) {
@@ -134,6 +135,7 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         l.kind = BatchLaunch::kTile;
         l.v = kv.first;
         l.n = items[kv.first];
+        l.out_bytes = obytes[kv.first];
         l.njobs = (int32_t)kv.second.size();
         const int64_t want = (l.n + kWavesPerBlock - 1) / kWavesPerBlock;
         int32_t cap = resident_blocks_cached(kv.first);
@@ -146,20 +148,25 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         launches.push_back(l);
         tables.push_back(std::move(kv.second));
     }
-    // Bin-major frames: one launch per bin-group width, one wave per item.
+    // Bin-major frames: one launch per bin-group width and columns per lane,
+    // one wave per item.
+    for (int cpl : {4, 1})
     for (int bg : {16, 8, 4, 2, 1}) {
         if (!binmajor) break;
         std::vector<Job> jobs;
-        int64_t begin = 0;
+        int64_t begin = 0, bm_bytes = 0;
         for (size_t k = 0; k < n; ++k) {
-            if (!(*binmajor)[k] || bm_group(frames[k].g.B) != bg) continue;
+            if (!(*binmajor)[k] || bm_group(frames[k].g.B) != bg || frames[k].g.CPL != cpl) continue;
             jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
             begin += tile_bm_items(frames[k].g);
+            bm_bytes += (int64_t)frames[k].g.H * frames[k].g.W * frames[k].g.B * 4;
         }
         if (jobs.empty()) continue;
         BatchLaunch l;
         l.kind = BatchLaunch::kTileBM;
         l.bg = bg;
+        l.cpl = cpl;
+        l.out_bytes = bm_bytes;
         l.n = begin;
         l.njobs = (int32_t)jobs.size();
         launches.push_back(l);
@@ -178,22 +185,27 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
     img->launches = std::move(launches);
 }
 
-hipError_t enqueue_batch(const BatchImage& img, const void* dev_image, int phase, hipStream_t s)
+hipError_t enqueue_launch(const BatchImage& img, const void* dev_image, size_t i, hipStream_t s)
 {
     const unsigned char* base = static_cast<const unsigned char*>(dev_image);
     const FrameArgs* fr = reinterpret_cast<const FrameArgs*>(base);
-    for (const BatchLaunch& l : img.launches) {
-        if (phase >= 0 && phase_of(l) != phase) continue;
-        const Job* jobs = reinterpret_cast<const Job*>(base + l.jobs_off);
-        hipError_t e = hipSuccess;
-        switch (l.kind) {
-        case BatchLaunch::kCount: e = launch_count_batch(l.tx, fr, jobs, l.njobs, l.n, l.lds, s); break;
-        case BatchLaunch::kScanA: e = launch_scan_a_batch(l.parts, fr, jobs, l.njobs, l.n, s); break;
-        case BatchLaunch::kScanB: e = launch_scan_b_batch(l.parts, fr, jobs, l.njobs, l.n, s); break;
-        case BatchLaunch::kTile: e = launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid, s); break;
-        case BatchLaunch::kTileBM: e = launch_tile_bm_batch(l.bg, fr, jobs, l.njobs, l.n, s); break;
-        }
-        if (e != hipSuccess) return e;
+    const BatchLaunch& l = img.launches[i];
+    const Job* jobs = reinterpret_cast<const Job*>(base + l.jobs_off);
+    switch (l.kind) {
+    case BatchLaunch::kCount: return launch_count_batch(l.tx, fr, jobs, l.njobs, l.n, l.lds, s);
+    case BatchLaunch::kScanA: return launch_scan_a_batch(l.parts, fr, jobs, l.njobs, l.n, s);
+    case BatchLaunch::kScanB: return launch_scan_b_batch(l.parts, fr, jobs, l.njobs, l.n, s);
+    case BatchLaunch::kTile: return launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid, s);
+    case BatchLaunch::kTileBM: return launch_tile_bm_batch(l.bg, l.cpl, fr, jobs, l.njobs, l.n, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t enqueue_batch(const BatchImage& img, const void* dev_image, int phase, hipStream_t s)
+{
+    for (size_t i = 0; i < img.launches.size(); ++i) {
+        if (phase >= 0 && phase_of(img.launches[i]) != phase) continue;
+        if (hipError_t e = enqueue_launch(img, dev_image, i, s)) return e;
     }
     return hipSuccess;
 }

@@ -15,12 +15,14 @@ struct BatchLaunch {
     int tx = 64;               // kCount: tile width of the frames it covers
     int parts = 1;             // kScanA, kScanB: scan form (scan_parts of its frames)
     int bg = 0;                // kTileBM: bins per work item of its frames
+    int cpl = 1;               // kTileBM: columns per lane of its frames
     TileVariant v{};           // kTile: compiled kernel variant
     size_t jobs_off = 0;       // byte offset of this launch's job table in the image
     int32_t njobs = 0;
     int64_t n = 0;             // blocks (kCount, kScan*) or work items (kTile, kTileBM)
     int32_t grid = 0;          // kTile: persistent workgroups
     size_t lds = 0;            // kCount: dynamic LDS bytes
+    int64_t out_bytes = 0;     // kTile, kTileBM: output bytes the launch writes (for balancing branches)
 };
 
 struct BatchImage {
@@ -32,8 +34,8 @@ struct BatchImage {
 size_t align_up(size_t v, size_t a);
 
 // Bytes of the largest launch image build_batch_image can make for n frames
-// (FrameArgs table, at most one count, four scan and 2 n + 5 tile launches,
-// seven jobs per frame, each table aligned to 256 bytes).
+// (FrameArgs table, at most three count, four scan, 2 n tile and ten
+// bin-major launches, seven jobs per frame, each table aligned to 256 bytes).
 size_t batch_image_bound(size_t n);
 
 // Scratch words a frame needs for the given tile.
@@ -51,6 +53,8 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
 // Enqueue the image's launches of one phase (-1: all phases) on s.  dev_image
 // is a device copy of img.host that stays valid until the work has run.
 hipError_t enqueue_batch(const BatchImage& img, const void* dev_image, int phase, hipStream_t s);
+// Enqueue launch i of the image on s.
+hipError_t enqueue_launch(const BatchImage& img, const void* dev_image, size_t i, hipStream_t s);
 
 int phase_of(const BatchLaunch& l);
 

@@ -148,7 +148,8 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
 
     // Column state: corner + running sum of the top carries along the segment.
     // Reduce-then-scan: the scans left tile (i, j)'s corner count and band
-    // i's top carries.  Fused: tile band i is band k of carry band I.  Its
+    // i's top carries.  Prefix counts: the top carries are stored as they
+    // are; the corner is the sum of the tile-column totals left of tile j.  Fused: tile band i is band k of carry band I.  Its
     // corner is the sum, over the carry bands above, of their pixels left of
     // the tile column, plus the pixels of carry band I's first k tile bands
     // left of it (snapshot k - 1); a column's top carry is its count above
@@ -160,7 +161,29 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
         const IH_GLOBAL uint32_t* colc = gmem(f.colc);
         const IH_GLOBAL uint32_t* tp;
         const IH_GLOBAL uint32_t* tq = nullptr;
-        if (g.K == 0) {
+        if (g.PC) {
+            // the totals of the tile columns to the left, 8 loads in flight
+            const IH_GLOBAL uint32_t* cp = corner + (size_t)i * g.nTX * B + b0;
+#pragma unroll
+            for (int t = 0; t < BPL; ++t) acc[t] = 0u;
+            int jp = 0;
+            for (; jp + 8 <= j; jp += 8) {
+                uint32_t v[8][BPL];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int t = 0; t < BPL; ++t) v[u][t] = bvalid[t] ? cp[(size_t)(jp + u) * B + t] : 0u;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int t = 0; t < BPL; ++t) acc[t] += v[u][t];
+            }
+            for (; jp < j; ++jp)
+#pragma unroll
+                for (int t = 0; t < BPL; ++t)
+                    if (bvalid[t]) acc[t] += cp[(size_t)jp * B + t];
+            tp = colc + ((size_t)i * g.W + x0) * B + b0;
+        } else if (g.K == 0) {
             const IH_GLOBAL uint32_t* cp = corner + ((size_t)i * g.nTX + j) * B + b0;
 #pragma unroll
             for (int t = 0; t < BPL; ++t) acc[t] = bvalid[t] ? cp[t] : 0u;

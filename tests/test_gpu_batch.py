@@ -101,6 +101,98 @@ def test_fused_carry_schedule(ihb, orc, tx, ty, k):
     plan.close()
 
 
+PREFIX = [(tx, ty) for tx in (32, 64, 128) for ty in (1, 8, 16, 64)]
+
+
+@pytest.mark.parametrize("tx,ty", PREFIX)
+def test_prefix_count_schedule(ihb, orc, tx, ty):
+    """The prefix-count schedule (each count block counts every row above its
+    band; the tile pass adds up the tile-column totals to its left; no scan
+    launch) on ragged frames of several bin counts, launched twice."""
+    rng = np.random.default_rng(tx * 7919 + ty)
+    shapes = [(300, 257, 64), (128, 640, 32), (97, 130, 128), (64, 192, 16), (50, 70, 3), (1, 64, 7), (17, 1, 5)]
+    if tx == 128:
+        shapes = [(300, 257, 64), (33, 384, 64), (17, 130, 64), (1, 64, 64), (5, 1, 64)]
+    if tx == 32:
+        shapes.append((70, 96, 256))
+    frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _ in shapes]
+    bins = [b for _, _, b in shapes]
+    refs = [orc.integral_histogram(f, b) for f, b in zip(frames, bins)]
+    fr, outs = to_dev(frames, bins)
+    plan = ihb.BatchPlan(fr, outs, bins, tile=(tx, ty), carry_bands=-2)
+    info = plan.info()
+    for j in range(len(shapes)):
+        sc = plan.frame_schedule(j)
+        assert sc["tile"] == (tx, ty) and sc["carry_bands"] == -2, (j, sc)
+    assert info["kernel_launches"] == 1 + info["tile_launches"], info       # no scan launches
+    for rep in range(2):
+        for o in outs:
+            o.fill_(0xA5A5A5A5)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for j in range(len(frames)):
+            assert np.array_equal(outs[j].cpu().numpy(), refs[j]), (rep, j, shapes[j])
+    plan.close()
+
+
+def test_three_schedules_in_one_launch(ihb, orc):
+    """In one plan a frame too tall for prefix counts (more than 65536 rows)
+    keeps reduce-then-scan while the others take prefix counts, all in the
+    same count and tile launches; then the same frames under the fused
+    schedule.  Every frame equals the oracle."""
+    rng = np.random.default_rng(80)
+    shapes = [(70000, 3, 4), (200, 300, 32), (64, 64, 16), (480, 640, 32)]
+    frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _ in shapes]
+    bins = [b for _, _, b in shapes]
+    fr, outs = to_dev(frames, bins)
+    plans = [ihb.BatchPlan(fr, outs, bins, tile=(32, 8), carry_bands=-2),
+             ihb.BatchPlan(fr, outs, bins, tile=(32, 8), carry_bands=3)]
+    assert plans[0].frame_schedule(0)["carry_bands"] == 0
+    assert all(plans[0].frame_schedule(j)["carry_bands"] == -2 for j in (1, 2, 3))
+    refs = [orc.integral_histogram(f, b) for f, b in zip(frames, bins)]
+    for plan in plans:
+        for o in outs:
+            o.fill_(0xA5A5A5A5)
+        plan.launch()
+        torch.cuda.synchronize()
+        for j in range(len(frames)):
+            assert np.array_equal(outs[j].cpu().numpy(), refs[j]), j
+        plan.close()
+
+
+@pytest.mark.parametrize("branches", [2, 3, 4])
+def test_tile_branches(ihb, orc, branches):
+    """Tile-pass launches of several kernel variants spread over graph
+    branches: graph launches, ungraphed launches and profiled launches (one
+    graph per phase) all equal the oracle, launch after launch, with eager
+    work on the stream between them."""
+    rng = np.random.default_rng(90 + branches)
+    shapes = [(300, 257, 64), (128, 640, 32), (97, 130, 128), (64, 192, 16), (50, 70, 3), (70, 96, 256),
+              (240, 320, 64), (33, 384, 16)]
+    frames = [rng.integers(0, 256, size=(h, w), dtype=np.uint8) for h, w, _ in shapes]
+    bins = [b for _, _, b in shapes]
+    refs = [orc.integral_histogram(f, b) for f, b in zip(frames, bins)]
+    fr, outs = to_dev(frames, bins)
+    for use_graph in (True, False):
+        plan = ihb.BatchPlan(fr, outs, bins, use_graph=use_graph, tile_branches=branches)
+        assert plan.info()["tile_launches"] >= 3
+        for rep in range(3):
+            for o in outs:
+                o.fill_(0xA5A5A5A5)
+            if rep == 2:
+                ihb.profile_enable(True)
+            plan.launch()
+            if rep == 2:
+                ph = ihb.profile_read()
+                ihb.profile_enable(False)
+                assert ph["tile_ms"] > 0
+            torch.cuda.synchronize()
+            for j in range(len(frames)):
+                assert np.array_equal(outs[j].cpu().numpy(), refs[j]), (use_graph, rep, j, shapes[j])
+        plan.close()
+
+
 def test_fused_and_reduce_then_scan_frames_in_one_launch(ihb, orc):
     """A frame too wide for the fused schedule's arrival counters keeps
     reduce-then-scan while the others take the fused one; all share the count
@@ -277,8 +369,10 @@ def test_autotuned_plan(ihb, orc):
     torch.cuda.synchronize()
     for k in range(4):
         tx, ty, _ = plan.frame_tile(k)
-        even = {-(-360 // -(-360 // t)) for t in (16, 32, 64, 128, 256)}   # bands made equally tall
+        even = {-(-360 // -(-360 // t)) for t in (8, 16, 32, 64, 128, 256)}   # bands made equally tall
         assert tx in (32, 64, 128) and ty in even
+        cb = plan.frame_schedule(k)["carry_bands"]
+        assert cb in (0, -2) or 1 <= cb <= -(-360 // ty), cb
         assert np.array_equal(outs[k].cpu().numpy(), orc.integral_histogram(frames[k], bins[k]))
     plan.close()
 
