@@ -228,7 +228,7 @@ typedef struct {
                                Frames whose geometry cannot take the schedule
                                asked for, and bin-major frames, keep
                                reduce-then-scan.                                 */
-    int32_t tile_branches;  /* 0: as chosen; 1: the tile-pass launches (one per
+    int32_t tile_branches;  /* 0: as chosen (four); 1: the tile-pass launches (one per
                                compiled kernel variant) run one after another;
                                2..4: they are spread over that many graph
                                branches (streams) that fork after the carry

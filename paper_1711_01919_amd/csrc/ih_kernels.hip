@@ -71,8 +71,9 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
     const int lane = threadIdx.x % kWave;
     uint32_t run[4] = {0u, 0u, 0u, 0u};
     const IH_GLOBAL uint8_t* prow = gmem(f.frame) + y * g.W;
-    // rowc is segment-major, [j][y][b]: a tile wave's rows are contiguous
-    IH_GLOBAL uint32_t* out = gmem(f.rowc) + y * B;
+    // rowc is segment-major, [j][y][b]: a tile wave's rows are contiguous;
+    // uint16 entries when RC16
+    const size_t row_off = (size_t)y * B;
     const size_t seg_stride = (size_t)g.H * B;
     // 16-byte chunks never straddle a segment (TX is a multiple of 16)
     const bool vec = ((reinterpret_cast<uintptr_t>(prow) & 15) == 0);
@@ -120,11 +121,12 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
         }
         wave_sync();
         for (int s = 0; s < ns; ++s) {
-            IH_GLOBAL uint32_t* o = out + (size_t)(j0 + s) * seg_stride;
+            const size_t o = row_off + (size_t)(j0 + s) * seg_stride;
             for (int t = 0; t < bpl; ++t) {
                 const int b = lane * bpl + t;
                 if (b < B) {
-                    o[b] = run[t];
+                    if (g.RC16) gmem(reinterpret_cast<uint16_t*>(f.rowc))[o + b] = (uint16_t)run[t];
+                    else gmem(f.rowc)[o + b] = run[t];
                     run[t] += lds_get8(lds, (uint32_t)(s * B + b));
                 }
             }
@@ -724,7 +726,7 @@ __device__ __forceinline__ void tile_bm_body(const FrameArgs& f, int64_t item)
         }
     }
     const IH_GLOBAL uint8_t* frame = gmem(f.frame);
-    const IH_GLOBAL uint32_t* rowc = gmem(f.rowc) + (size_t)j * H * B + b_lo;
+    const size_t rowc_base = (size_t)j * H * B + b_lo;
     IH_GLOBAL uint32_t* out = gmem(f.out);
     const size_t plane = (size_t)H * W;
     // Pixels (CPL per lane, packed) and left carries come 8 rows at a time, a
@@ -752,7 +754,7 @@ __device__ __forceinline__ void tile_bm_body(const FrameArgs& f, int64_t item)
                     if (k < nvalid) w |= (uint32_t)p[k] << (8 * k);
                 q[r] = w;
             }
-            c[r] = lane < BG ? rowc[(size_t)row * B + lane] : 0u;
+            c[r] = lane < BG ? left_carry(f, rowc_base + (size_t)row * B + lane) : 0u;
         }
     };
     load_chunk(y0, cq, cc);

@@ -10,6 +10,11 @@
 
 namespace ih {
 
+// s_waitcnt operand that waits for the LDS/scalar-memory counter to reach zero
+// and leaves the vector-memory and export counters unconstrained (gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt in 6:4, lgkmcnt in 11:8).
+constexpr int kWaitLgkm0 = 0xC07F;
+
 // ---------------------------------------------------------------------------
 // Phase 3: the tile pass (hot loop)
 // ---------------------------------------------------------------------------
@@ -62,18 +67,29 @@ __device__ __forceinline__ void load_px(const FrameArgs& f, int y, int x0, int n
 }
 
 // Left carries of CH consecutive rows y, y+1, ... of segment j (rows past the
-// band clamped to its last row): CH x B contiguous uint32 in the segment-major
-// rowc, read as one burst.
+// band clamped to its last row): CH x B contiguous entries (uint16, or uint32
+// for frames wider than 65536) in the segment-major rowc, read as one burst.
 template <int BPL, int CH>
 __device__ __forceinline__ void load_carries(const FrameArgs& f, int y, int y_last, int j, int b0, int B,
                                              const bool (&bvalid)[BPL], uint32_t (&cb)[CH][BPL])
 {
-    const IH_GLOBAL uint32_t* rp = gmem(f.rowc) + (size_t)j * f.g.H * B + b0;
+    const size_t base = (size_t)j * f.g.H * B + b0;
+    if (f.g.RC16) {
+        const IH_GLOBAL uint16_t* rp = gmem(reinterpret_cast<const uint16_t*>(f.rowc)) + base;
 #pragma unroll
-    for (int q = 0; q < CH; ++q) {
-        const IH_GLOBAL uint32_t* r = rp + (size_t)min(y + q, y_last) * B;
+        for (int q = 0; q < CH; ++q) {
+            const IH_GLOBAL uint16_t* r = rp + (size_t)min(y + q, y_last) * B;
 #pragma unroll
-        for (int t = 0; t < BPL; ++t) cb[q][t] = bvalid[t] ? r[t] : 0u;
+            for (int t = 0; t < BPL; ++t) cb[q][t] = bvalid[t] ? (uint32_t)r[t] : 0u;
+        }
+    } else {
+        const IH_GLOBAL uint32_t* rp = gmem(f.rowc) + base;
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const IH_GLOBAL uint32_t* r = rp + (size_t)min(y + q, y_last) * B;
+#pragma unroll
+            for (int t = 0; t < BPL; ++t) cb[q][t] = bvalid[t] ? r[t] : 0u;
+        }
     }
 }
 
@@ -341,6 +357,18 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
         }
         return;
     }
+    // Scalar loads (the pixels of one-segment waves) may return out of order,
+    // so a wait for one of them is a wait for all: the row being started
+    // waits for its own pixels (loaded a row earlier) before the next row's
+    // loads go out, and the compiler then needs no wait that would cover
+    // those.
+    auto wait_scalar = [&]() {
+        if constexpr (UNIFORM && !GUARD) {
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
     uint32_t pxa[TX / 4], pxb[TX / 4];
     load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
     load_px<TX, GUARD, UNIFORM>(f, y0, x0, ncols, pxa);
@@ -352,6 +380,7 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
 #pragma unroll 1
         for (int r = 0; r < CH; r += 2) {
             const int y = yc + r;
+            wait_scalar();
             load_px<TX, GUARD, UNIFORM>(f, min(y + 1, y1 - 1), x0, ncols, pxb);
             __builtin_amdgcn_sched_barrier(0);        // keep the prefetch ahead of the stores
             if (y < y1) row_pass(y, pxa, cb[0]);
@@ -359,6 +388,7 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
             for (int q = 0; q + 1 < CH; ++q)
 #pragma unroll
                 for (int t = 0; t < BPL; ++t) cb[q][t] = cb[q + 1][t];
+            wait_scalar();
             load_px<TX, GUARD, UNIFORM>(f, min(y + 2, y1 - 1), x0, ncols, pxa);
             __builtin_amdgcn_sched_barrier(0);
             if (y + 1 < y1) row_pass(y + 1, pxb, cb[0]);

@@ -60,6 +60,24 @@ def test_video_sizes(ihb, orc, H, W, B):
     assert np.array_equal(gpu_ih(ihb, I, B), orc.integral_histogram(I, B))
 
 
+@pytest.mark.parametrize("H,W,B", [(2, 65536, 1), (3, 65536, 5), (2, 65537, 1), (3, 70001, 3), (1, 131072, 2)])
+def test_wide_frames_left_carry_widths(ihb, orc, H, W, B):
+    """Left carries are kept as uint16 up to 65536 columns (the largest, at the
+    last segment of a B=1 frame, is 65536 - TX) and as uint32 beyond: every
+    single-frame form equals the oracle on both sides of the boundary."""
+    rng = np.random.default_rng(H * 7 + W + B)
+    I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    if B == 1:
+        I[:] = 200                          # every pixel in the one bin: carries as large as they get
+    want = orc.integral_histogram(I, B)
+    f = torch.from_numpy(I).cuda()
+    assert np.array_equal(ihb.compute(f, B).cpu().numpy(), want)
+    bm = ihb.compute_binmajor(f, B)
+    assert np.array_equal(bm.permute(1, 2, 0).contiguous().cpu().numpy(), want)
+    lut = ((np.arange(256) * B) >> 8).astype(np.uint8)
+    assert np.array_equal(ihb.compute_lut(f, B, lut).cpu().numpy(), want)
+
+
 def test_unaligned_frame_and_output(ihb, orc):
     """Frame and output views that start off a 16-byte boundary take the
     guarded kernel and must give the same bits."""
