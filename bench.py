@@ -41,7 +41,36 @@ HBM_PEAK_GBS = 8000.0
 # reads on the same counters), summed over the tile-pass dispatches of one
 # step.  Valid only for the kernel sources and schedule they were taken with;
 # any other combination reports null.
-TRAFFIC_RECORDS = {}
+TRAFFIC_RECORDS = {
+    "uneven_batch_256": {
+        "kernel_sources_sha256": "c12ddf86e68ad4b95bd07c05dd5ae2315f31ef2bab041bc601872fb24ea766de",
+        "schedule": {
+            "1080x1920 B128": "64x216 nt reduce-then-scan",
+            "1080x1920 B16": "32x120 reduce-then-scan",
+            "1080x1920 B32": "64x120 reduce-then-scan",
+            "1080x1920 B64": "32x120 nt reduce-then-scan",
+            "2160x3840 B128": "64x128 reduce-then-scan",
+            "2160x3840 B16": "64x128 reduce-then-scan",
+            "2160x3840 B32": "64x240 reduce-then-scan",
+            "2160x3840 B64": "128x240 reduce-then-scan",
+            "240x320 B128": "32x60 nt prefix counts",
+            "240x320 B16": "32x8 nt prefix counts",
+            "240x320 B32": "32x30 prefix counts",
+            "240x320 B64": "32x30 nt prefix counts",
+            "480x640 B128": "64x120 nt prefix counts",
+            "480x640 B16": "32x60 prefix counts",
+            "480x640 B32": "32x60 prefix counts",
+            "480x640 B64": "32x120 prefix counts",
+            "720x1280 B128": "64x120 nt reduce-then-scan",
+            "720x1280 B16": "32x120 nt prefix counts",
+            "720x1280 B32": "32x240 nt reduce-then-scan",
+            "720x1280 B64": "64x240 nt reduce-then-scan"
+        },
+        "fetch_bytes": 2640703889,
+        "write_bytes": 126786056704,
+        "source": "profiles/uneven_batch_256_tile_pass_hbm_counters.md"
+    }
+}
 
 KERNEL_SOURCES = ["ih_kernels.hip", "ih_tile.h", "ih_device.h", "ih_internal.h", "ih_tile_regular.hip",
                   "ih_tile_regular_guarded.hip", "ih_tile_nontemporal.hip", "ih_tile_nontemporal_guarded.hip",
@@ -350,8 +379,9 @@ def schedule_summary(plan, frames, bins):
         key = f"{f.shape[0]}x{f.shape[1]} B{b}"
         if key not in seen:
             sc = plan.frame_schedule(k)
-            seen[key] = (f"{sc['tile'][0]}x{sc['tile'][1]}" + (" nt" if sc["nontemporal"] else "") +
-                         (f" fused K={sc['carry_bands']}" if sc["carry_bands"] else " reduce-then-scan"))
+            cb = sc["carry_bands"]
+            sched = " prefix counts" if cb == -2 else (f" fused K={cb}" if cb > 0 else " reduce-then-scan")
+            seen[key] = f"{sc['tile'][0]}x{sc['tile'][1]}" + (" nt" if sc["nontemporal"] else "") + sched
     return dict(sorted(seen.items()))
 
 
