@@ -648,8 +648,9 @@ def run_legs(torch, ihb, synth, stream, args, want, legs) -> None:
         legs["disc_sequence_64x1080x1920_B64"] = disc_sequence_leg(torch, ihb, synth, stream, args)
         log(f"[bench] disc sequence: {legs['disc_sequence_64x1080x1920_B64']}")
     if "plain" in want:
-        legs.update(plain_and_query_legs(torch, ihb, synth, stream))
-        log("[bench] plain/query legs done")
+        pl = plain_and_query_legs(torch, ihb, synth, stream)
+        legs.update(pl)
+        log(f"[bench] plain/query legs: {pl}")
     if "transfer" in want:
         legs["transfer_pipeline"] = transfer_leg(torch, ihb)
         log(f"[bench] transfer pipeline: {legs['transfer_pipeline']}")

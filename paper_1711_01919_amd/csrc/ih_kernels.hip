@@ -162,14 +162,44 @@ __device__ __forceinline__ uint32_t lds_get16(const uint32_t* h, uint32_t e)
 }
 
 // Pixels of rows [ya, yb) and columns [x0, x0 + tw) added to the per-column
-// bin counters colh (thread tid takes column tid % TX of every
-// (kAggThreads / TX)-th row).
+// bin counters colh.  Rows whose four-byte words are aligned (W a multiple
+// of 4, frame 4-byte aligned; tw is then a multiple of 4 too): thread tid
+// takes the four columns 4 (tid % (TX/4)) .. + 3 of every (kAggThreads /
+// (TX/4))-th row with one load.  Otherwise thread tid takes column tid % TX
+// of every (kAggThreads / TX)-th row.
 template <int TX>
 __device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* lutw, uint32_t* colh, int ya, int yb,
                                            int x0, int tw)
 {
-    constexpr int kRowsPerPass = kAggThreads / TX;
     const Geom& g = f.g;
+    if ((g.W % 4) == 0 && (reinterpret_cast<uintptr_t>(f.frame) & 3) == 0) {
+        constexpr int TPR = TX / 4;                    // threads per row
+        constexpr int kRowsPerPass4 = kAggThreads / TPR;
+        const int tr = (int)threadIdx.x / TPR, tq = (int)threadIdx.x % TPR;
+        if (4 * tq >= tw) return;
+        const int th = yb - ya;
+        const size_t stride = (size_t)(g.W / 4);
+        const IH_GLOBAL uint32_t* p =
+            reinterpret_cast<const IH_GLOBAL uint32_t*>(gmem(f.frame) + (size_t)ya * g.W + x0) + tq;
+        constexpr int U = 8;
+        for (int r0 = tr; r0 < th; r0 += U * kRowsPerPass4) {
+            uint32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = r0 + u * kRowsPerPass4;
+                v[u] = r < th ? p[(size_t)r * stride] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (r0 + u * kRowsPerPass4 < th)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        lds_inc16(colh, (uint32_t)((4 * tq + c) * g.B) +
+                                            bin_of(f, lutw, (v[u] >> (8 * c)) & 0xFFu, (uint32_t)g.B));
+        }
+        return;
+    }
+    constexpr int kRowsPerPass = kAggThreads / TX;
     const int tr = (int)threadIdx.x / TX, tx = (int)threadIdx.x % TX;
     if (tx >= tw) return;
     const int th = yb - ya;
