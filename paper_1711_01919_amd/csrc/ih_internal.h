@@ -198,9 +198,11 @@ hipError_t launch_scan_a_batch(int parts, const FrameArgs* frames, const Job* jo
                                int64_t nblocks, hipStream_t stream);
 hipError_t launch_scan_b_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
                                int64_t nblocks, hipStream_t stream);
-// Persistent tile launch: `grid` workgroups loop over `nitems` work items.
+// Persistent tile launch: `grid` workgroups loop over `nitems` work items,
+// taking them from the scheduling counter `sched` (two words, zero at launch
+// and zero again after it) or, when it is null, striding over them.
 hipError_t launch_tile_batch(const TileVariant& v, const FrameArgs* frames, const Job* jobs,
-                             int32_t njobs, int64_t nitems, int32_t grid, hipStream_t stream);
+                             int32_t njobs, int64_t nitems, int32_t grid, uint32_t* sched, hipStream_t stream);
 // Workgroups of the tile kernel that fit on the device at once.
 int32_t tile_resident_blocks(const TileVariant& v);
 

@@ -1065,11 +1065,11 @@ hipError_t launch_scan_b_batch(int parts, const FrameArgs* frames, const Job* jo
 }
 
 hipError_t launch_tile_batch(const TileVariant& v, const FrameArgs* frames, const Job* jobs,
-                             int32_t njobs, int64_t nitems, int32_t grid, hipStream_t stream)
+                             int32_t njobs, int64_t nitems, int32_t grid, uint32_t* sched, hipStream_t stream)
 {
     if (nitems <= 0) return hipSuccess;
     const TileFns fn = tile_fns(v);
-    void* args[] = {&frames, &jobs, &njobs, &nitems};
+    void* args[] = {&frames, &jobs, &njobs, &nitems, &sched};
     hipError_t e = hipLaunchKernel(fn.batch, dim3((unsigned)grid), dim3(kWave * kWavesPerBlock), args, 0, stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();

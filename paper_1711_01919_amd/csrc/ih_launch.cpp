@@ -15,7 +15,7 @@ size_t frame_scratch_words(const Geom& g) { return align_up(scratch_layout(g).wo
 size_t batch_image_bound(size_t n)
 {
     const size_t launches = 3 + 4 + 2 * n + 10;
-    return align_up(n * sizeof(FrameArgs), 256) + launches * 256 + 7 * n * sizeof(Job) + 256;
+    return align_up(n * sizeof(FrameArgs), 256) + launches * 256 + 7 * n * sizeof(Job) + 256 + 2 * n * 256;
 }
 
 int phase_of(const BatchLaunch& l)
@@ -114,8 +114,12 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         launches.push_back(l);
         tables.push_back(std::move(jobs));
     }
-    std::map<TileVariant, std::vector<Job>> byv;
-    std::map<TileVariant, int64_t> items, obytes;
+    // Tile jobs per kernel variant, the jobs with the largest work items
+    // first (a persistent wave takes the next item when it finishes one, so
+    // the small items fill in at the end).
+    struct TileJob { Job job; int64_t items, item_bytes; };
+    std::map<TileVariant, std::vector<TileJob>> pending;
+    std::map<TileVariant, int64_t> obytes;
     for (size_t k = 0; k < n; ++k) {
         if (binmajor && (*binmajor)[k]) continue;
         const Geom& g = frames[k].g;
@@ -124,10 +128,22 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         for (int q = 0; q < 2; ++q) {
             if (parts[q][1] <= 0) continue;
             const TileVariant v = tile_variant(g, nontemporal[k] != 0, q == 1, frames[k].lut != nullptr);
-            int64_t& b = items[v];
-            byv[v].push_back(Job{b, (int32_t)k, parts[q][0], parts[q][1], 0});
-            b += (int64_t)g.nTY * parts[q][1];
+            const int64_t item_bytes = (int64_t)g.TY * std::min<int64_t>((int64_t)g.S * g.TX, g.W) * g.B * 4;
+            pending[v].push_back(TileJob{Job{0, (int32_t)k, parts[q][0], parts[q][1], 0},
+                                         (int64_t)g.nTY * parts[q][1], item_bytes});
             obytes[v] += (int64_t)g.H * g.W * g.B * 4 * parts[q][1] / g.nJG;
+        }
+    }
+    std::map<TileVariant, std::vector<Job>> byv;
+    std::map<TileVariant, int64_t> items;
+    for (auto& kv : pending) {
+        std::stable_sort(kv.second.begin(), kv.second.end(),
+                         [](const TileJob& a, const TileJob& b) { return a.item_bytes > b.item_bytes; });
+        int64_t& b = items[kv.first];
+        for (TileJob& t : kv.second) {
+            t.job.begin = b;
+            byv[kv.first].push_back(t.job);
+            b += t.items;
         }
     }
     for (auto& kv : byv) {
@@ -178,6 +194,14 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         launches[t].jobs_off = bytes;
         bytes = align_up(bytes + tables[t].size() * sizeof(Job), 256);
     }
+    // scheduling counters of the tile launches, zero in the image, each in a
+    // 256-byte line of its own (away from the tables, which are read through
+    // the scalar cache)
+    for (BatchLaunch& l : launches) {
+        if (l.kind != BatchLaunch::kTile) continue;
+        l.sched_off = bytes;
+        bytes += 256;
+    }
     img->host.assign(bytes, 0);
     std::memcpy(img->host.data(), frames.data(), n * sizeof(FrameArgs));
     for (size_t t = 0; t < tables.size(); ++t)
@@ -195,7 +219,11 @@ hipError_t enqueue_launch(const BatchImage& img, const void* dev_image, size_t i
     case BatchLaunch::kCount: return launch_count_batch(l.tx, fr, jobs, l.njobs, l.n, l.lds, s);
     case BatchLaunch::kScanA: return launch_scan_a_batch(l.parts, fr, jobs, l.njobs, l.n, s);
     case BatchLaunch::kScanB: return launch_scan_b_batch(l.parts, fr, jobs, l.njobs, l.n, s);
-    case BatchLaunch::kTile: return launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid, s);
+    case BatchLaunch::kTile:
+        return launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid,
+                                 l.sched_off ? reinterpret_cast<uint32_t*>(const_cast<unsigned char*>(base) + l.sched_off)
+                                             : nullptr,
+                                 s);
     case BatchLaunch::kTileBM: return launch_tile_bm_batch(l.bg, l.cpl, fr, jobs, l.njobs, l.n, s);
     }
     return hipErrorInvalidValue;

@@ -23,6 +23,7 @@ struct BatchLaunch {
     int32_t grid = 0;          // kTile: persistent workgroups
     size_t lds = 0;            // kCount: dynamic LDS bytes
     int64_t out_bytes = 0;     // kTile, kTileBM: output bytes the launch writes (for balancing branches)
+    size_t sched_off = 0;      // kTile: byte offset of its two-word scheduling counter in the image (zero there)
 };
 
 struct BatchImage {
@@ -35,7 +36,8 @@ size_t align_up(size_t v, size_t a);
 
 // Bytes of the largest launch image build_batch_image can make for n frames
 // (FrameArgs table, at most three count, four scan, 2 n tile and ten
-// bin-major launches, seven jobs per frame, each table aligned to 256 bytes).
+// bin-major launches, seven jobs per frame, each table aligned to 256 bytes,
+// and a 256-byte scheduling counter per tile launch).
 size_t batch_image_bound(size_t n);
 
 // Scratch words a frame needs for the given tile.

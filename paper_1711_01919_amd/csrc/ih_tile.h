@@ -415,22 +415,44 @@ void tile_kernel(FrameArgs f, int32_t jg_begin, int32_t jg_count)
     tile_body<BPL, TX, BC, NT, GUARD, TABLE>(f, i, jg, threadIdx.x % kWave);
 }
 
-// Persistent form: each wave strides over the work items of all jobs.
+// Persistent form over the work items of all jobs.  With a scheduling
+// counter (sched: next item, waves finished; both zero at launch) each wave
+// takes the next item from the counter when it finishes one, so waves that
+// drew small items take more of them (the job table lists the largest items
+// first); the last wave to finish resets both words for the next launch.
+// Without one, each wave strides over the items.
 template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE>
 __global__ __launch_bounds__(kWave * kWavesPerBlock)
 void tile_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs,
-                       int32_t njobs, int64_t nitems)
+                       int32_t njobs, int64_t nitems, uint32_t* sched)
 {
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block(); item < nitems;
-         item += stride) {
+    auto run = [&](int64_t item) {
         const Job jb = cload(jobs, find_job(cmem(jobs), njobs, item));
         const int64_t local = item - jb.begin;
         const int i = (int)(local / jb.jg_count);
         const int jg = jb.jg_begin + (int)(local - (int64_t)i * jb.jg_count);
         const FrameArgs f = cload(frames, jb.frame);
         tile_body<BPL, TX, BC, NT, GUARD, TABLE>(f, i, jg, threadIdx.x % kWave);
+    };
+    if (sched) {
+        const bool leader = threadIdx.x % kWave == 0;
+        for (;;) {
+            uint32_t got = 0;
+            if (leader) got = atomicAdd(&sched[0], 1u);
+            const int64_t item = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)got);
+            if (item >= nitems) break;                        // whole wave leaves together
+            run(item);
+        }
+        if (leader && atomicAdd(&sched[1], 1u) == gridDim.x * (uint32_t)kWavesPerBlock - 1u) {
+            // every wave has taken its last item: nobody reads the counter again in this launch
+            atomicExch(&sched[0], 0u);
+            atomicExch(&sched[1], 0u);
+        }
+        return;
     }
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block(); item < nitems; item += stride)
+        run(item);
 }
 
 template <int BPL, int TX, int BC, bool NT, bool GUARD, bool TABLE = false>
