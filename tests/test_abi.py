@@ -152,3 +152,21 @@ def test_batch_plan_rejects_bad_tables_and_layouts_before_launch(lib):
               FrameDesc(fake, fake, 4, 4, 8, ctypes.cast(good, ctypes.c_void_p), 1)):  # bin-major with a table
         assert f((FrameDesc * 1)(d), 1, None, None, ctypes.byref(plan)) == 1
         assert not plan.value
+
+
+def test_batch_options_rejected_before_launch(lib):
+    """Carry schedule codes below -2 and tile branches outside 0..4 are argument
+    errors, reported before any descriptor is read or device call made."""
+    class Options(ctypes.Structure):
+        _fields_ = [("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                    ("tile_y", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("group_bytes", ctypes.c_int64),
+                    ("carry_bands", ctypes.c_int32), ("tile_branches", ctypes.c_int32)]
+    f = lib.ih_batch_plan_create
+    f.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(Options), ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_void_p)]
+    fake = 0x1000  # never dereferenced: validation fails first
+    plan = ctypes.c_void_p()
+    for bad in (Options(0, 1, 0, 0, -1, 0, -3, 0), Options(0, 1, 0, 0, -1, 0, -1, 5),
+                Options(0, 1, 0, 0, -1, 0, -1, -1)):
+        assert f(fake, 1, ctypes.byref(bad), None, ctypes.byref(plan)) == 1
+        assert not plan.value
