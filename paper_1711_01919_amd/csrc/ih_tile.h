@@ -162,14 +162,48 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
         }
     }
 
+    // Left carries and pixels, a chunk of rows at a time (see below); the
+    // first chunk's loads go out before the column state's, so that every
+    // load the work item needs before its first store is in flight at once.
+    // Several segments per wave (B < 64, compile-time B, whole segments):
+    // the pixels of a chunk of rows for all of the wave's segments come in
+    // one wave-wide load, and each lane fetches its segment's bytes of a row
+    // from the lane holding them (ds_bpermute).  Piece p (16 bytes) of a
+    // chunk is row r, 16-byte column c, segment s with p = (r * PPR + c) * SC
+    // + s, held by lane p.
+    constexpr int SC = kWave / LC;
+    constexpr int PPR = TX / 16;
+    constexpr bool CHUNK_PX = !GUARD && !UNIFORM && BC != 0 && SC * PPR <= kWave;
+    constexpr int CH = CHUNK_PX ? (8 / BPL < kWave / (SC * PPR) ? 8 / BPL : kWave / (SC * PPR)) : 8 / BPL;
+    uint32_t cb[CH][BPL], nb[CH][BPL];
+    auto load_chunk_px = [&](int yc, u32x4& dst) {
+        const int p = lane < CH * SC * PPR ? lane : 0;
+        const int ps = p % SC, pc_ = (p / SC) % PPR, pr = p / (SC * PPR);
+        const int row = min(yc + pr, y1 - 1);
+        const int px0 = (jg * SC + ps) * TX + 16 * pc_;
+        dst = *reinterpret_cast<const IH_GLOBAL u32x4*>(gmem(f.frame) + (size_t)row * g.W + px0);
+    };
+    u32x4 pc, pn;
+    uint32_t pxa[TX / 4], pxb[TX / 4];
+    load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
+    if constexpr (CHUNK_PX) {
+        static_assert(CH * SC * PPR <= kWave, "a pixel chunk must fit one wave-wide load");
+        load_chunk_px(y0, pc);
+    } else {
+        load_px<TX, GUARD, UNIFORM>(f, y0, x0, ncols, pxa);
+    }
+
     // Column state: corner + running sum of the top carries along the segment.
     // Reduce-then-scan: the scans left tile (i, j)'s corner count and band
     // i's top carries.  Prefix counts: the top carries are stored as they
-    // are; the corner is the sum of the tile-column totals left of tile j.  Fused: tile band i is band k of carry band I.  Its
-    // corner is the sum, over the carry bands above, of their pixels left of
-    // the tile column, plus the pixels of carry band I's first k tile bands
-    // left of it (snapshot k - 1); a column's top carry is its count above
-    // carry band I plus the same snapshot's count.
+    // are; the corner is the sum of the tile-column totals left of tile j.
+    // Fused: tile band i is band k of carry band I.  Its corner is the sum,
+    // over the carry bands above, of their pixels left of the tile column,
+    // plus the pixels of carry band I's first k tile bands left of it
+    // (snapshot k - 1); a column's top carry is its count above carry band I
+    // plus the same snapshot's count.  The top carries are loaded into V
+    // first and the corner terms after them; masked-off terms read a valid
+    // address and add zero, so no load waits behind a branch.
     uint32_t V[BPL][TX];
     {
         uint32_t acc[BPL];
@@ -177,72 +211,81 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
         const IH_GLOBAL uint32_t* colc = gmem(f.colc);
         const IH_GLOBAL uint32_t* tp;
         const IH_GLOBAL uint32_t* tq = nullptr;
+        const int K = g.K, I = K ? i / K : 0, k_in = i - I * K;
+        if (g.PC || K == 0) {
+            tp = colc + ((size_t)i * g.W + x0) * B + b0;
+        } else {
+            tp = colc + (((size_t)I * K + K - 1) * g.W + x0) * B + b0;
+            if (k_in > 0) tq = colc + (((size_t)I * K + k_in - 1) * g.W + x0) * B + b0;
+        }
+#pragma unroll
+        for (int k = 0; k < TX; ++k)
+#pragma unroll
+            for (int t = 0; t < BPL; ++t) {
+                const bool ok = k < ncols && bvalid[t];
+                const uint32_t v = *(ok ? tp + (size_t)k * B + t : colc);
+                V[t][k] = ok ? v : 0u;
+            }
+        if (tq) {
+#pragma unroll
+            for (int k = 0; k < TX; ++k)
+#pragma unroll
+                for (int t = 0; t < BPL; ++t) {
+                    const bool ok = k < ncols && bvalid[t];
+                    const uint32_t v = *(ok ? tq + (size_t)k * B + t : colc);
+                    V[t][k] += ok ? v : 0u;
+                }
+        }
+#pragma unroll
+        for (int t = 0; t < BPL; ++t) acc[t] = 0u;
         if (g.PC) {
-            // the totals of the tile columns to the left, 8 loads in flight
+            // the totals of the tile columns to the left, LB columns of loads
+            // in flight together
+            constexpr int LB = TX * BPL <= 32 ? 16 : 8;
             const IH_GLOBAL uint32_t* cp = corner + (size_t)i * g.nTX * B + b0;
+            for (int jp = 0; jp < j; jp += LB) {
+                uint32_t v[LB][BPL];
 #pragma unroll
-            for (int t = 0; t < BPL; ++t) acc[t] = 0u;
-            int jp = 0;
-            for (; jp + 8 <= j; jp += 8) {
-                uint32_t v[8][BPL];
+                for (int u = 0; u < LB; ++u)
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                    for (int t = 0; t < BPL; ++t) {
+                        const bool ok = jp + u < j && bvalid[t];
+                        v[u][t] = *(ok ? cp + (size_t)(jp + u) * B + t : corner);
+                        v[u][t] = ok ? v[u][t] : 0u;
+                    }
+                // all of the chunk's loads issue before any of them is waited for
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int t = 0; t < BPL; ++t) v[u][t] = bvalid[t] ? cp[(size_t)(jp + u) * B + t] : 0u;
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < LB; ++u)
 #pragma unroll
                     for (int t = 0; t < BPL; ++t) acc[t] += v[u][t];
             }
-            for (; jp < j; ++jp)
-#pragma unroll
-                for (int t = 0; t < BPL; ++t)
-                    if (bvalid[t]) acc[t] += cp[(size_t)jp * B + t];
-            tp = colc + ((size_t)i * g.W + x0) * B + b0;
-        } else if (g.K == 0) {
+        } else if (K == 0) {
             const IH_GLOBAL uint32_t* cp = corner + ((size_t)i * g.nTX + j) * B + b0;
 #pragma unroll
             for (int t = 0; t < BPL; ++t) acc[t] = bvalid[t] ? cp[t] : 0u;
-            tp = colc + ((size_t)i * g.W + x0) * B + b0;
         } else {
-            const int K = g.K, I = i / K, k = i - I * K;
             const size_t band_words = (size_t)K * g.nTX * B;
             const IH_GLOBAL uint32_t* cq = corner + ((size_t)(K - 1) * g.nTX + j) * B + b0;
-#pragma unroll
-            for (int t = 0; t < BPL; ++t) acc[t] = 0u;
 #pragma unroll 4
             for (int ip = 0; ip < I; ++ip)
 #pragma unroll
                 for (int t = 0; t < BPL; ++t)
                     if (bvalid[t]) acc[t] += cq[(size_t)ip * band_words + t];
-            tp = colc + (((size_t)I * K + K - 1) * g.W + x0) * B + b0;
-            if (k > 0) {
-                const IH_GLOBAL uint32_t* cp = corner + (((size_t)I * K + k - 1) * g.nTX + j) * B + b0;
+            if (k_in > 0) {
+                const IH_GLOBAL uint32_t* cp = corner + (((size_t)I * K + k_in - 1) * g.nTX + j) * B + b0;
 #pragma unroll
                 for (int t = 0; t < BPL; ++t)
                     if (bvalid[t]) acc[t] += cp[t];
-                tq = colc + (((size_t)I * K + k - 1) * g.W + x0) * B + b0;
             }
         }
-        if (tq) {
 #pragma unroll
-            for (int k = 0; k < TX; ++k) {
+        for (int k = 0; k < TX; ++k)
 #pragma unroll
-                for (int t = 0; t < BPL; ++t) {
-                    if (k < ncols && bvalid[t]) acc[t] += tp[(size_t)k * B + t] + tq[(size_t)k * B + t];
-                    V[t][k] = acc[t];
-                }
+            for (int t = 0; t < BPL; ++t) {
+                acc[t] += V[t][k];
+                V[t][k] = acc[t];
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < TX; ++k) {
-#pragma unroll
-                for (int t = 0; t < BPL; ++t) {
-                    if (k < ncols && bvalid[t]) acc[t] += tp[(size_t)k * B + t];
-                    V[t][k] = acc[t];
-                }
-            }
-        }
     }
 
     const bool vec_ok = (b0 + BPL <= B) && (B % BPL == 0) &&
@@ -302,29 +345,7 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
     // share one in-order completion counter on this architecture, so a load
     // issued after a row's stores could only be waited for behind them.
     // Rows past the band are clamped, so every wave runs the same control flow.
-    // Several segments per wave (B < 64, compile-time B, whole segments):
-    // the pixels of a chunk of rows for all of the wave's segments come in
-    // one wave-wide load too, and each lane fetches its segment's bytes of a
-    // row from the lane holding them (ds_bpermute).  Piece p (16 bytes) of a
-    // chunk is row r, 16-byte column c, segment s with p = (r * PPR + c) * SC
-    // + s, held by lane p.
-    constexpr int SC = kWave / LC;
-    constexpr int PPR = TX / 16;
-    constexpr bool CHUNK_PX = !GUARD && !UNIFORM && BC != 0 && SC * PPR <= kWave;
-    constexpr int CH = CHUNK_PX ? (8 / BPL < kWave / (SC * PPR) ? 8 / BPL : kWave / (SC * PPR)) : 8 / BPL;
-    uint32_t cb[CH][BPL], nb[CH][BPL];
     if constexpr (CHUNK_PX) {
-        static_assert(CH * SC * PPR <= kWave, "a pixel chunk must fit one wave-wide load");
-        auto load_chunk_px = [&](int yc, u32x4& dst) {
-            const int p = lane < CH * SC * PPR ? lane : 0;
-            const int ps = p % SC, pc_ = (p / SC) % PPR, pr = p / (SC * PPR);
-            const int row = min(yc + pr, y1 - 1);
-            const int px0 = (jg * SC + ps) * TX + 16 * pc_;
-            dst = *reinterpret_cast<const IH_GLOBAL u32x4*>(gmem(f.frame) + (size_t)row * g.W + px0);
-        };
-        u32x4 pc, pn;
-        load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
-        load_chunk_px(y0, pc);
         __builtin_amdgcn_s_waitcnt(0);
         for (int yc = y0; yc < y1; yc += CH) {
             const bool more = yc + CH < y1;
@@ -369,9 +390,6 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    uint32_t pxa[TX / 4], pxb[TX / 4];
-    load_carries<BPL, CH>(f, y0, y1 - 1, j, b0, B, bvalid, cb);
-    load_px<TX, GUARD, UNIFORM>(f, y0, x0, ncols, pxa);
     // Drain everything once per work item, so that inside the loop the
     // compiler's counter bookkeeping sees only the in-loop prefetches.
     __builtin_amdgcn_s_waitcnt(0);
