@@ -187,17 +187,17 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
 
 // ---- batched launches over a device FrameArgs table ----------------------
 // Count phase (row carries + tile column counts) of many frames of tile width
-// TX in one launch; a job's jg_begin holds its frame's row-carry block count.
-hipError_t launch_count_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+// TX and one kind of schedule (fused, or not) in one launch; a job's jg_begin
+// holds its frame's row-carry block count.
+hipError_t launch_count_batch(int TX, bool fused, const FrameArgs* frames, const Job* jobs, int32_t njobs,
                               int64_t nblocks, size_t lds_bytes, hipStream_t stream);
 // Row-carry blocks (four rows each) and dynamic LDS bytes of a frame's count phase.
 int32_t count_row_blocks(const Geom& g);
 size_t count_lds(const Geom& g);
-// `parts` is scan_parts() of every frame the launch covers.
-hipError_t launch_scan_a_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
-                               int64_t nblocks, hipStream_t stream);
-hipError_t launch_scan_b_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
-                               int64_t nblocks, hipStream_t stream);
+// The scan phase of many frames in one launch; `parts` is scan_parts(nTY) of
+// every frame the launch covers.
+hipError_t launch_scan_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+                             int64_t nblocks, hipStream_t stream);
 // Persistent tile launch: `grid` workgroups loop over `nitems` work items,
 // taking them from the scheduling counter `sched` (two words, zero at launch
 // and zero again after it) or, when it is null, striding over them.
@@ -206,15 +206,23 @@ hipError_t launch_tile_batch(const TileVariant& v, const FrameArgs* frames, cons
 // Workgroups of the tile kernel that fit on the device at once.
 int32_t tile_resident_blocks(const TileVariant& v);
 
-// Blocks of the scan kernels for one frame.
+// Blocks of the scan launch for one frame.
 // Carry sequences longer than one 16-element chunk are split over the
-// kScanParts waves of a scan block; shorter ones take one thread each.
-// scan_a's sequences run over the nTY bands, scan_b's over the nTX tile columns.
+// kScanParts waves of a scan block; shorter ones take one thread each.  The
+// column-count sequences run over the nTY bands; the tile totals are scanned
+// in two dimensions by blocks of corner_bins_per_block bins each: grids of at
+// most 64 x 64 tiles take one sequence per lane and pass (split over the
+// block's waves), larger ones one bin per block and one sequence per thread.
 constexpr int kScanParts = kScanThreads / kWave;
 inline int scan_parts(int len) { return len > 16 ? kScanParts : 1; }
 inline int scan_per_block(int len) { return kScanThreads / scan_parts(len); }
-int64_t scan_a_blocks(const Geom& g);
-int64_t scan_b_blocks(const Geom& g);
+__host__ __device__ inline int corner_bins_per_block(const Geom& g)
+{
+    const int m = g.nTX > g.nTY ? g.nTX : g.nTY;
+    const int nb = m > kWave ? 1 : kWave / m;
+    return nb < g.B ? nb : g.B;
+}
+int64_t scan_blocks(const Geom& g);
 
 // Tile pass writing the bin-major layout (entry (x, y, b) at (b*H + y)*W + x)
 // from the carries of a frame whose geometry has 64-column tiles.

@@ -120,16 +120,33 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
             }
         }
         wave_sync();
-        for (int s = 0; s < ns; ++s) {
-            const size_t o = row_off + (size_t)(j0 + s) * seg_stride;
-            for (int t = 0; t < bpl; ++t) {
-                const int b = lane * bpl + t;
-                if (b < B) {
-                    if (g.RC16) gmem(reinterpret_cast<uint16_t*>(f.rowc))[o + b] = (uint16_t)run[t];
-                    else gmem(f.rowc)[o + b] = run[t];
-                    run[t] += lds_get8(lds, (uint32_t)(s * B + b));
+        // Per bin of the lane: the counters of four segments at a time are
+        // read from LDS together, then the running counts are stored
+        // segment by segment.
+        for (int t = 0; t < bpl; ++t) {
+            const int b = lane * bpl + t;
+            if (b >= B) break;
+            uint32_t r = run[t];
+#pragma unroll 1
+            for (int s0 = 0; s0 < ns; s0 += 4) {
+                uint32_t c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = s0 + u < ns;
+                    const uint32_t v = lds_get8(lds, ok ? (uint32_t)((s0 + u) * B + b) : 0u);
+                    c[u] = ok ? v : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (s0 + u < ns) {
+                        const size_t o = row_off + (size_t)(j0 + s0 + u) * seg_stride + b;
+                        if (g.RC16) gmem(reinterpret_cast<uint16_t*>(f.rowc))[o] = (uint16_t)r;
+                        else gmem(f.rowc)[o] = r;
+                    }
+                    r += c[u];
                 }
             }
+            run[t] = r;
         }
         wave_sync();
     }
@@ -257,19 +274,19 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
 // in flight at once.
 __device__ __forceinline__ void scan_seq(IH_GLOBAL uint32_t* p, int64_t stride, int len, uint32_t run)
 {
+    // chunks of C elements, the last one masked: all loads of a chunk go out
+    // before any of its stores (a store may alias a later load as far as the
+    // compiler knows, so a load issued after it would wait for it)
     constexpr int C = 16;
-    int k = 0;
-    for (; k + C <= len; k += C) {
+    for (int k = 0; k < len; k += C) {
         uint32_t v[C];
 #pragma unroll
-        for (int u = 0; u < C; ++u) v[u] = p[(k + u) * stride];
+        for (int u = 0; u < C; ++u) v[u] = k + u < len ? p[(k + u) * stride] : 0u;
 #pragma unroll
-        for (int u = 0; u < C; ++u) { p[(k + u) * stride] = run; run += v[u]; }
-    }
-    for (; k < len; ++k) {
-        const uint32_t v = p[k * stride];
-        p[k * stride] = run;
-        run += v;
+        for (int u = 0; u < C; ++u) {
+            if (k + u < len) p[(k + u) * stride] = run;
+            run += v[u];
+        }
     }
 }
 
@@ -277,15 +294,13 @@ __device__ __forceinline__ uint32_t sum_seq(const IH_GLOBAL uint32_t* p, int64_t
 {
     constexpr int C = 16;
     uint32_t s = 0;
-    int k = 0;
-    for (; k + C <= len; k += C) {
+    for (int k = 0; k < len; k += C) {
         uint32_t v[C];
 #pragma unroll
-        for (int u = 0; u < C; ++u) v[u] = p[(k + u) * stride];
+        for (int u = 0; u < C; ++u) v[u] = k + u < len ? p[(k + u) * stride] : 0u;
 #pragma unroll
         for (int u = 0; u < C; ++u) s += v[u];
     }
-    for (; k < len; ++k) s += p[k * stride];
     return s;
 }
 
@@ -436,13 +451,16 @@ __host__ __device__ inline size_t agg_lds_bytes(int TX, int B)
     return ((size_t)TX * B + 1) / 2 * 4 + 256 + (size_t)B * 4 + 8;
 }
 
-// The tile-block role of the count launch, by schedule.
-template <int TX>
+// The tile-block role of the count launch, by schedule.  The fused
+// schedule's blocks hold a band of pixels in registers; it is compiled into
+// kernels of its own (FUSED), so that the other count kernels keep a small
+// register footprint and every block of a launch is resident at once.
+template <int TX, bool FUSED>
 __device__ __forceinline__ void agg_role(const FrameArgs& f, int64_t blk, uint32_t* lds)
 {
     uint32_t* colh = lds;
     uint32_t* lutw = colh + ((size_t)TX * f.g.B + 1) / 2;
-    if (f.g.K) {
+    if constexpr (FUSED) {
         uint32_t* tot = lutw + 64;
         agg_fused_body<TX>(f, blk, colh, lutw, tot, tot + f.g.B);
     } else {
@@ -450,7 +468,7 @@ __device__ __forceinline__ void agg_role(const FrameArgs& f, int64_t blk, uint32
     }
 }
 
-template <int TX>
+template <int TX, bool FUSED>
 __global__ __launch_bounds__(kAggThreads)
 void count_kernel(FrameArgs f, int32_t row_blocks)
 {
@@ -461,10 +479,10 @@ void count_kernel(FrameArgs f, int32_t row_blocks)
         if (y < f.g.H) rowcarry_body(f, y, lds + (size_t)w * (rowcarry_lds_bytes(f.g) / 4));
         return;
     }
-    agg_role<TX>(f, (int64_t)blockIdx.x - row_blocks, lds);
+    agg_role<TX, FUSED>(f, (int64_t)blockIdx.x - row_blocks, lds);
 }
 
-template <int TX>
+template <int TX, bool FUSED>
 __global__ __launch_bounds__(kAggThreads)
 void count_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
@@ -478,7 +496,7 @@ void count_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restr
         if (y < f.g.H) rowcarry_body(f, y, lds + (size_t)w * (rowcarry_lds_bytes(f.g) / 4));
         return;
     }
-    agg_role<TX>(f, local - jb.jg_begin, lds);
+    agg_role<TX, FUSED>(f, local - jb.jg_begin, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -536,74 +554,77 @@ __device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t st
     }
 }
 
-// Column counts across tile bands and tile totals across bands --
-// independent sequences of length nTY; the frame's blocks take the column
-// sequences first, then the tile-total ones, so that each block holds one
-// kind.  `blk` is the block's index within the frame's scan blocks.
+// The scan launch.  Its first blocks scan the column counts down the tile
+// bands (independent sequences of length nTY, one per column and bin): top
+// carries.  The rest scan the tile totals in two dimensions, each block for
+// its own bins: first down the bands for every tile column, then -- after a
+// block barrier, which makes the first pass's stores visible to the whole
+// block -- across the tile columns for every band, leaving corner[i][j][b] =
+// the pixels above and to the left of tile (i, j).  `blk` is the block's
+// index within the frame's scan blocks.
+__device__ __forceinline__ void corner_scan(const FrameArgs& f, int64_t cb, uint32_t* sums)
+{
+    const Geom& g = f.g;
+    const int B = g.B;
+    const int nb = corner_bins_per_block(g);
+    const int b_lo = (int)cb * nb;
+    const int nbh = min(nb, B - b_lo);
+    IH_GLOBAL uint32_t* corner = gmem(f.corner) + b_lo;
+    const int64_t row = (int64_t)g.nTX * B;                  // words between bands
+    if (max(g.nTX, g.nTY) <= kWave) {
+        // one sequence per lane and pass, each split over the block's waves
+        const int lane = (int)threadIdx.x % kWave;
+        const int q1 = g.nTX * nbh, q2 = g.nTY * nbh;         // both <= kWave
+        {
+            const int j = lane < q1 ? lane / nbh : 0, t = lane < q1 ? lane - j * nbh : 0;
+            scan_seq_parts<kScanParts>(corner + (int64_t)j * B + t, row, g.nTY, lane < q1, sums);
+        }
+        __syncthreads();
+        {
+            const int i = lane < q2 ? lane / nbh : 0, t = lane < q2 ? lane - i * nbh : 0;
+            scan_seq_parts<kScanParts>(corner + i * row + t, B, g.nTX, lane < q2, sums);
+        }
+        return;
+    }
+    // larger grids (one bin per block): one sequence per thread
+    const int q1 = g.nTX, q2 = g.nTY;
+    for (int q = (int)threadIdx.x; q < q1; q += kScanThreads) scan_seq(corner + (int64_t)q * B, row, g.nTY, 0u);
+    __syncthreads();
+    for (int q = (int)threadIdx.x; q < q2; q += kScanThreads) scan_seq(corner + q * row, B, g.nTX, 0u);
+}
+
 template <int P>
-__device__ __forceinline__ void scan_a_body(const FrameArgs& f, int64_t blk, uint32_t* sums)
+__device__ __forceinline__ void scan_body(const FrameArgs& f, int64_t blk, uint32_t* sums)
 {
     const Geom& g = f.g;
     const int64_t B = g.B;
     constexpr int per = kScanThreads / P;
-    const int64_t ncol = (int64_t)g.W * B, ntot = (int64_t)g.nTX * B;
+    const int64_t ncol = (int64_t)g.W * B;
     const int64_t col_blocks = (ncol + per - 1) / per;
-    const bool is_col = blk < col_blocks;                    // uniform over the block
-    const int64_t t = (is_col ? blk : blk - col_blocks) * per + (int)threadIdx.x % per;
-    IH_GLOBAL uint32_t* base = is_col ? gmem(f.colc) : gmem(f.corner);
-    const int64_t stride = (is_col ? (int64_t)g.W : (int64_t)g.nTX) * B;
-    scan_seq_parts<P>(base + t, stride, g.nTY, t < (is_col ? ncol : ntot), sums);
-}
-
-// Band-scanned tile totals across tile columns (sequences of length nTX):
-// corner[i][j][b] becomes the count of pixels above and to the left of tile
-// (i, j).
-template <int P>
-__device__ __forceinline__ void scan_b_body(const FrameArgs& f, int64_t blk, uint32_t* sums)
-{
-    const Geom& g = f.g;
-    const int64_t B = g.B;
-    constexpr int per = kScanThreads / P;
+    if (blk >= col_blocks) {                                  // uniform over the block
+        corner_scan(f, blk - col_blocks, sums);
+        return;
+    }
     const int64_t t = blk * per + (int)threadIdx.x % per;
-    const bool active = t < (int64_t)g.nTY * B;
-    const int64_t i = t / B, b = t - i * B;
-    scan_seq_parts<P>(gmem(f.corner) + i * g.nTX * B + b, B, g.nTX, active, sums);
+    scan_seq_parts<P>(gmem(f.colc) + t, (int64_t)g.W * B, g.nTY, t < ncol, sums);
 }
 
 template <int P>
 __global__ __launch_bounds__(kScanThreads)
-void scan_a_kernel(FrameArgs f)
+void scan_kernel(FrameArgs f)
 {
-    __shared__ uint32_t sums[P == 1 ? 1 : kScanThreads];
-    scan_a_body<P>(f, blockIdx.x, sums);
+    __shared__ uint32_t sums[kScanThreads];
+    scan_body<P>(f, blockIdx.x, sums);
 }
 
 template <int P>
 __global__ __launch_bounds__(kScanThreads)
-void scan_b_kernel(FrameArgs f)
+void scan_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
 {
-    __shared__ uint32_t sums[P == 1 ? 1 : kScanThreads];
-    scan_b_body<P>(f, blockIdx.x, sums);
-}
-
-template <int P>
-__global__ __launch_bounds__(kScanThreads)
-void scan_a_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
-{
-    __shared__ uint32_t sums[P == 1 ? 1 : kScanThreads];
+    __shared__ uint32_t sums[kScanThreads];
     const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
     const FrameArgs f = cload(frames, jb.frame);
-    scan_a_body<P>(f, (int64_t)blockIdx.x - jb.begin, sums);
-}
-
-template <int P>
-__global__ __launch_bounds__(kScanThreads)
-void scan_b_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restrict__ jobs, int32_t njobs)
-{
-    __shared__ uint32_t sums[P == 1 ? 1 : kScanThreads];
-    const Job jb = cload(jobs, find_job(cmem(jobs), njobs, blockIdx.x));
-    const FrameArgs f = cload(frames, jb.frame);
-    scan_b_body<P>(f, (int64_t)blockIdx.x - jb.begin, sums);
+    scan_body<P>(f, (int64_t)blockIdx.x - jb.begin, sums);
 }
 
 // ---------------------------------------------------------------------------
@@ -926,18 +947,42 @@ void lut_store_kernel(LutArg a, uint32_t* dst)
 // host side: launches (geometry and tile choice live in ih_geom.cpp, the
 // tile kernels in ih_tile_*.hip)
 // ---------------------------------------------------------------------------
+// The count kernel of a tile width and schedule (single-frame or batched form).
+static const void* count_fn(int TX, bool fused, bool batched)
+{
+    if (batched) {
+        if (fused)
+            return TX == 32 ? reinterpret_cast<const void*>(&count_batch_kernel<32, true>)
+                 : TX == 128 ? reinterpret_cast<const void*>(&count_batch_kernel<128, true>)
+                             : reinterpret_cast<const void*>(&count_batch_kernel<64, true>);
+        return TX == 32 ? reinterpret_cast<const void*>(&count_batch_kernel<32, false>)
+             : TX == 128 ? reinterpret_cast<const void*>(&count_batch_kernel<128, false>)
+                         : reinterpret_cast<const void*>(&count_batch_kernel<64, false>);
+    }
+    if (fused)
+        return TX == 32 ? reinterpret_cast<const void*>(&count_kernel<32, true>)
+             : TX == 128 ? reinterpret_cast<const void*>(&count_kernel<128, true>)
+                         : reinterpret_cast<const void*>(&count_kernel<64, true>);
+    return TX == 32 ? reinterpret_cast<const void*>(&count_kernel<32, false>)
+         : TX == 128 ? reinterpret_cast<const void*>(&count_kernel<128, false>)
+                     : reinterpret_cast<const void*>(&count_kernel<64, false>);
+}
+
 hipError_t preload_kernels()
 {
     std::vector<const void*> fns = {
-        reinterpret_cast<const void*>(&count_kernel<32>), reinterpret_cast<const void*>(&count_kernel<64>),
-        reinterpret_cast<const void*>(&count_kernel<128>), reinterpret_cast<const void*>(&count_batch_kernel<32>),
-        reinterpret_cast<const void*>(&count_batch_kernel<64>), reinterpret_cast<const void*>(&count_batch_kernel<128>),
-        reinterpret_cast<const void*>(&scan_a_kernel<1>), reinterpret_cast<const void*>(&scan_a_kernel<kScanParts>),
-        reinterpret_cast<const void*>(&scan_b_kernel<1>), reinterpret_cast<const void*>(&scan_b_kernel<kScanParts>),
-        reinterpret_cast<const void*>(&scan_a_batch_kernel<1>),
-        reinterpret_cast<const void*>(&scan_a_batch_kernel<kScanParts>),
-        reinterpret_cast<const void*>(&scan_b_batch_kernel<1>),
-        reinterpret_cast<const void*>(&scan_b_batch_kernel<kScanParts>),
+        reinterpret_cast<const void*>(&count_kernel<32, false>), reinterpret_cast<const void*>(&count_kernel<64, false>),
+        reinterpret_cast<const void*>(&count_kernel<128, false>), reinterpret_cast<const void*>(&count_kernel<32, true>),
+        reinterpret_cast<const void*>(&count_kernel<64, true>), reinterpret_cast<const void*>(&count_kernel<128, true>),
+        reinterpret_cast<const void*>(&count_batch_kernel<32, false>),
+        reinterpret_cast<const void*>(&count_batch_kernel<64, false>),
+        reinterpret_cast<const void*>(&count_batch_kernel<128, false>),
+        reinterpret_cast<const void*>(&count_batch_kernel<32, true>),
+        reinterpret_cast<const void*>(&count_batch_kernel<64, true>),
+        reinterpret_cast<const void*>(&count_batch_kernel<128, true>),
+        reinterpret_cast<const void*>(&scan_kernel<1>), reinterpret_cast<const void*>(&scan_kernel<kScanParts>),
+        reinterpret_cast<const void*>(&scan_batch_kernel<1>),
+        reinterpret_cast<const void*>(&scan_batch_kernel<kScanParts>),
         reinterpret_cast<const void*>(&query_kernel<false>), reinterpret_cast<const void*>(&query_kernel<true>),
         reinterpret_cast<const void*>(&lut_store_kernel)};
     // one kernel of every tile-pass source (each source is one code object)
@@ -957,16 +1002,11 @@ hipError_t preload_kernels()
     return hipSuccess;
 }
 
-int64_t scan_a_blocks(const Geom& g)
+int64_t scan_blocks(const Geom& g)
 {
     const int64_t per = scan_per_block(g.nTY);
-    return ((int64_t)g.W * g.B + per - 1) / per + ((int64_t)g.nTX * g.B + per - 1) / per;
-}
-
-int64_t scan_b_blocks(const Geom& g)
-{
-    const int64_t per = scan_per_block(g.nTX);
-    return ((int64_t)g.nTY * g.B + per - 1) / per;
+    const int nb = corner_bins_per_block(g);
+    return ((int64_t)g.W * g.B + per - 1) / per + (g.B + nb - 1) / nb;
 }
 
 hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStream_t stream)
@@ -977,25 +1017,20 @@ hipError_t launch_phase(Phase ph, const FrameArgs& f, bool nontemporal, hipStrea
         const int32_t row_blocks = count_row_blocks(g);
         const unsigned blocks = (unsigned)row_blocks + (unsigned)count_tile_blocks(g);
         const size_t lds = count_lds(g);
-        if (g.TX == 32)
-            hipLaunchKernelGGL(count_kernel<32>, dim3(blocks), dim3(kAggThreads), (unsigned)lds, stream, f, row_blocks);
-        else if (g.TX == 128)
-            hipLaunchKernelGGL(count_kernel<128>, dim3(blocks), dim3(kAggThreads), (unsigned)lds, stream, f, row_blocks);
-        else
-            hipLaunchKernelGGL(count_kernel<64>, dim3(blocks), dim3(kAggThreads), (unsigned)lds, stream, f, row_blocks);
+        const void* fn = count_fn(g.TX, g.K != 0, false);
+        FrameArgs fa = f;
+        int32_t rb = row_blocks;
+        void* args[] = {&fa, &rb};
+        hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(kAggThreads), args, lds, stream);
+        if (e != hipSuccess) return e;
         break;
     }
     case Phase::kScan:
         if (g.K || g.PC) break;         // fused or prefix counts: no scan launch
         if (scan_parts(g.nTY) == 1)
-            hipLaunchKernelGGL(scan_a_kernel<1>, dim3((unsigned)scan_a_blocks(g)), dim3(kScanThreads), 0, stream, f);
+            hipLaunchKernelGGL(scan_kernel<1>, dim3((unsigned)scan_blocks(g)), dim3(kScanThreads), 0, stream, f);
         else
-            hipLaunchKernelGGL(scan_a_kernel<kScanParts>, dim3((unsigned)scan_a_blocks(g)), dim3(kScanThreads), 0,
-                               stream, f);
-        if (scan_parts(g.nTX) == 1)
-            hipLaunchKernelGGL(scan_b_kernel<1>, dim3((unsigned)scan_b_blocks(g)), dim3(kScanThreads), 0, stream, f);
-        else
-            hipLaunchKernelGGL(scan_b_kernel<kScanParts>, dim3((unsigned)scan_b_blocks(g)), dim3(kScanThreads), 0,
+            hipLaunchKernelGGL(scan_kernel<kScanParts>, dim3((unsigned)scan_blocks(g)), dim3(kScanThreads), 0,
                                stream, f);
         break;
     case Phase::kTile: {
@@ -1026,41 +1061,27 @@ size_t count_lds(const Geom& g)
     return std::max(kRowsPerCountBlock * rowcarry_lds_bytes(g), agg_lds_bytes(g.TX, g.B));
 }
 
-hipError_t launch_count_batch(int TX, const FrameArgs* frames, const Job* jobs, int32_t njobs,
+hipError_t launch_count_batch(int TX, bool fused, const FrameArgs* frames, const Job* jobs, int32_t njobs,
                               int64_t nblocks, size_t lds_bytes, hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
-    const dim3 grid((unsigned)nblocks), block(kAggThreads);
-    if (TX == 32)
-        hipLaunchKernelGGL(count_batch_kernel<32>, grid, block, (unsigned)lds_bytes, stream, frames, jobs, njobs);
-    else if (TX == 128)
-        hipLaunchKernelGGL(count_batch_kernel<128>, grid, block, (unsigned)lds_bytes, stream, frames, jobs, njobs);
-    else
-        hipLaunchKernelGGL(count_batch_kernel<64>, grid, block, (unsigned)lds_bytes, stream, frames, jobs, njobs);
-    return hipGetLastError();
+    const void* fn = count_fn(TX, fused, true);
+    const FrameArgs* fa = frames;
+    const Job* jb = jobs;
+    int32_t nj = njobs;
+    void* args[] = {&fa, &jb, &nj};
+    return hipLaunchKernel(fn, dim3((unsigned)nblocks), dim3(kAggThreads), args, lds_bytes, stream);
 }
 
-hipError_t launch_scan_a_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
-                               int64_t nblocks, hipStream_t stream)
+hipError_t launch_scan_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs, int64_t nblocks,
+                             hipStream_t stream)
 {
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid((unsigned)nblocks), block(kScanThreads);
     if (parts == 1)
-        hipLaunchKernelGGL(scan_a_batch_kernel<1>, grid, block, 0, stream, frames, jobs, njobs);
+        hipLaunchKernelGGL(scan_batch_kernel<1>, grid, block, 0, stream, frames, jobs, njobs);
     else
-        hipLaunchKernelGGL(scan_a_batch_kernel<kScanParts>, grid, block, 0, stream, frames, jobs, njobs);
-    return hipGetLastError();
-}
-
-hipError_t launch_scan_b_batch(int parts, const FrameArgs* frames, const Job* jobs, int32_t njobs,
-                               int64_t nblocks, hipStream_t stream)
-{
-    if (nblocks <= 0) return hipSuccess;
-    const dim3 grid((unsigned)nblocks), block(kScanThreads);
-    if (parts == 1)
-        hipLaunchKernelGGL(scan_b_batch_kernel<1>, grid, block, 0, stream, frames, jobs, njobs);
-    else
-        hipLaunchKernelGGL(scan_b_batch_kernel<kScanParts>, grid, block, 0, stream, frames, jobs, njobs);
+        hipLaunchKernelGGL(scan_batch_kernel<kScanParts>, grid, block, 0, stream, frames, jobs, njobs);
     return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ size_t frame_scratch_words(const Geom& g) { return align_up(scratch_layout(g).wo
 
 size_t batch_image_bound(size_t n)
 {
-    const size_t launches = 3 + 4 + 2 * n + 10;
+    const size_t launches = 6 + 2 + 2 * n + 10;
     return align_up(n * sizeof(FrameArgs), 256) + launches * 256 + 7 * n * sizeof(Job) + 256 + 2 * n * 256;
 }
 
@@ -22,8 +22,7 @@ int phase_of(const BatchLaunch& l)
 {
     switch (l.kind) {
     case BatchLaunch::kCount: return 0;
-    case BatchLaunch::kScanA:
-    case BatchLaunch::kScanB: return 1;
+    case BatchLaunch::kScan: return 1;
     default: return 2;
     }
 }
@@ -65,16 +64,18 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
     std::vector<std::vector<Job>> tables;
     std::vector<BatchLaunch> launches;
 
-    // Count phase, one launch per tile width: per frame, row-carry blocks of
-    // four rows (jg_begin of the job holds their count), then one block per
-    // tile (reduce-then-scan) or per carry band and tile column (fused).
-    for (int tx : {32, 64, 128}) {
+    // Count phase, one launch per tile width and kind of schedule (fused or
+    // not): per frame, row-carry blocks of four rows (jg_begin of the job
+    // holds their count), then one block per tile (reduce-then-scan, prefix
+    // counts) or per carry band and tile column (fused).
+    for (int tx : {32, 64, 128})
+    for (bool fused : {false, true}) {
         std::vector<Job> jobs;
         int64_t begin = 0;
         size_t lds = 0;
         for (size_t k = 0; k < n; ++k) {
             const Geom& g = frames[k].g;
-            if (g.TX != tx) continue;
+            if (g.TX != tx || (g.K != 0) != fused) continue;
             const int32_t row_blocks = count_row_blocks(g);
             jobs.push_back(Job{begin, (int32_t)k, row_blocks, 0, 0});
             begin += row_blocks + count_tile_blocks(g);
@@ -84,30 +85,30 @@ void build_batch_image(const std::vector<FrameArgs>& frames, const std::vector<c
         BatchLaunch l;
         l.kind = BatchLaunch::kCount;
         l.tx = tx;
+        l.fused = fused;
         l.lds = lds;
         l.n = begin;
         l.njobs = (int32_t)jobs.size();
         launches.push_back(l);
         tables.push_back(std::move(jobs));
     }
-    // Scans: one launch per kind and per scan form (one thread per carry
-    // sequence, or sequences split over the waves of a block).
-    for (BatchLaunch::Kind kind : {BatchLaunch::kScanA, BatchLaunch::kScanB})
+    // Scans: one launch per scan form (one thread per carry sequence, or
+    // sequences split over the waves of a block).
     for (int parts : {1, kScanParts}) {
         std::vector<Job> jobs;
         int64_t begin = 0;
         for (size_t k = 0; k < n; ++k) {
             const Geom& g = frames[k].g;
             if (g.K || g.PC) continue;  // fused or prefix counts: carries ready after the count launch
-            if (scan_parts(kind == BatchLaunch::kScanA ? g.nTY : g.nTX) != parts) continue;
-            const int64_t nb = kind == BatchLaunch::kScanA ? scan_a_blocks(g) : scan_b_blocks(g);
+            if (scan_parts(g.nTY) != parts) continue;
+            const int64_t nb = scan_blocks(g);
             if (nb == 0) continue;
             jobs.push_back(Job{begin, (int32_t)k, 0, 0, 0});
             begin += nb;
         }
         if (jobs.empty()) continue;
         BatchLaunch l;
-        l.kind = kind;
+        l.kind = BatchLaunch::kScan;
         l.parts = parts;
         l.n = begin;
         l.njobs = (int32_t)jobs.size();
@@ -216,9 +217,8 @@ hipError_t enqueue_launch(const BatchImage& img, const void* dev_image, size_t i
     const BatchLaunch& l = img.launches[i];
     const Job* jobs = reinterpret_cast<const Job*>(base + l.jobs_off);
     switch (l.kind) {
-    case BatchLaunch::kCount: return launch_count_batch(l.tx, fr, jobs, l.njobs, l.n, l.lds, s);
-    case BatchLaunch::kScanA: return launch_scan_a_batch(l.parts, fr, jobs, l.njobs, l.n, s);
-    case BatchLaunch::kScanB: return launch_scan_b_batch(l.parts, fr, jobs, l.njobs, l.n, s);
+    case BatchLaunch::kCount: return launch_count_batch(l.tx, l.fused, fr, jobs, l.njobs, l.n, l.lds, s);
+    case BatchLaunch::kScan: return launch_scan_batch(l.parts, fr, jobs, l.njobs, l.n, s);
     case BatchLaunch::kTile:
         return launch_tile_batch(l.v, fr, jobs, l.njobs, l.n, l.grid,
                                  l.sched_off ? reinterpret_cast<uint32_t*>(const_cast<unsigned char*>(base) + l.sched_off)

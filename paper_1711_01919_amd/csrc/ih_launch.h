@@ -11,15 +11,16 @@
 namespace ih {
 
 struct BatchLaunch {
-    enum Kind { kCount, kScanA, kScanB, kTile, kTileBM } kind = kCount;
+    enum Kind { kCount, kScan, kTile, kTileBM } kind = kCount;
     int tx = 64;               // kCount: tile width of the frames it covers
-    int parts = 1;             // kScanA, kScanB: scan form (scan_parts of its frames)
+    bool fused = false;        // kCount: its frames take the fused carry schedule
+    int parts = 1;             // kScan: scan form (scan_parts of its frames)
     int bg = 0;                // kTileBM: bins per work item of its frames
     int cpl = 1;               // kTileBM: columns per lane of its frames
     TileVariant v{};           // kTile: compiled kernel variant
     size_t jobs_off = 0;       // byte offset of this launch's job table in the image
     int32_t njobs = 0;
-    int64_t n = 0;             // blocks (kCount, kScan*) or work items (kTile, kTileBM)
+    int64_t n = 0;             // blocks (kCount, kScan) or work items (kTile, kTileBM)
     int32_t grid = 0;          // kTile: persistent workgroups
     size_t lds = 0;            // kCount: dynamic LDS bytes
     int64_t out_bytes = 0;     // kTile, kTileBM: output bytes the launch writes (for balancing branches)
@@ -35,7 +36,7 @@ struct BatchImage {
 size_t align_up(size_t v, size_t a);
 
 // Bytes of the largest launch image build_batch_image can make for n frames
-// (FrameArgs table, at most three count, four scan, 2 n tile and ten
+// (FrameArgs table, at most six count, two scan, 2 n tile and ten
 // bin-major launches, seven jobs per frame, each table aligned to 256 bytes,
 // and a 256-byte scheduling counter per tile launch).
 size_t batch_image_bound(size_t n);
