@@ -58,11 +58,19 @@ __device__ __forceinline__ void load_px(const FrameArgs& f, int y, int x0, int n
             px[4 * q + 2] = w.z; px[4 * q + 3] = w.w;
         }
     } else {
+        // A whole segment whose row starts on a four-byte boundary: dword
+        // loads.  Otherwise (the frame's right edge, or rows that are not
+        // word-aligned) byte loads of the pixels inside the frame.
+        if (ncols == TX && (reinterpret_cast<uintptr_t>(prow) & 3) == 0) {
 #pragma unroll
-        for (int q = 0; q < TX / 4; ++q) px[q] = 0u;
+            for (int q = 0; q < TX / 4; ++q) px[q] = reinterpret_cast<const IH_GLOBAL uint32_t*>(prow)[q];
+        } else {
 #pragma unroll
-        for (int k = 0; k < TX; ++k)
-            if (k < ncols) px[k / 4] |= (uint32_t)prow[k] << (8 * (k % 4));
+            for (int q = 0; q < TX / 4; ++q) px[q] = 0u;
+#pragma unroll
+            for (int k = 0; k < TX; ++k)
+                if (k < ncols) px[k / 4] |= (uint32_t)prow[k] << (8 * (k % 4));
+        }
     }
 }
 
