@@ -216,7 +216,7 @@ typedef struct {
                                all phases in order (default)                     */
     int32_t carry_bands;    /* carry schedule.  -1: as chosen (heuristic, or
                                autotuned per class); 0: reduce-then-scan (a count
-                               launch, two scan launches, the tile pass); K >= 1:
+                               launch, a scan launch, the tile pass); K >= 1:
                                fused -- the count launch counts bands of K tile
                                bands and scans the carries itself, so the tile
                                pass follows it directly (K is clamped to a frame's

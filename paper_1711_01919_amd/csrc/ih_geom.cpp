@@ -92,8 +92,29 @@ int32_t even_band_height(int32_t H, int32_t TY)
 TileChoice default_tile(int32_t H, int32_t W, int32_t B)
 {
     TileChoice t;
-    t.TX = bins_per_lane(B) == 4 ? 32 : 64;
     t.nontemporal = false;
+    // Frames up to 1920 x 1080 with B <= 64: measured one-frame sweeps (ten
+    // shapes from 640 x 480 to 1920 x 1080, B = 16 to 64) favour 32-column
+    // tiles and fewer, taller bands than the rule below (1920 x 1080 B=32:
+    // 70.0 us at 32 x 64 against 88.6 us at 64 x 16; B=64: 126 against 132 us
+    // at 64 x 32; 640 x 480 B=64: 28.4 against 32.3 us), as long as a band's
+    // work items stay below about 640 KB of output (1920 x 1080 B=64 at
+    // 32 x 128: 146 us) and leave some 450 of them.
+    if (bins_per_lane(B) == 1 && (int64_t)H * W <= kMidFramePixels) {
+        t.TX = 32;
+        const Geom g0 = make_geom(H, W, B, TileChoice{32, 1, false});
+        const int64_t row_bytes = (int64_t)g0.S * 32 * B * 4;      // a work item's output per row
+        auto bands = [&](int ty) { return (H + ty - 1) / ty; };
+        int TY = 512;
+        while (TY > 8 && ((int64_t)bands(TY) * g0.nJG < kMidFrameWaves || row_bytes * TY > kMidFrameItemBytes))
+            TY /= 2;
+        t.TY = TY;
+        t.prefix = bands(TY) <= kMaxPrefixBands && (int64_t)H * W * bands(TY) / 2 <= kMidPrefixPixels;
+        t.TY = even_band_height(H, t.TY);
+        if (t.prefix && !prefix_supported(make_geom(H, W, B, t))) t.prefix = false;
+        return t;
+    }
+    t.TX = bins_per_lane(B) == 4 ? 32 : 64;
     // Tallest tile (fewest carries) that still gives about 1000 independent
     // waves (one per work item in a single-frame launch): measured best for
     // 1080p to 8K frames at B = 16 to 64, against both half and twice that.

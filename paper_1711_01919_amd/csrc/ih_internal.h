@@ -57,6 +57,14 @@ constexpr int32_t kMaxPrefixBands = 64;
 // Pixels the count blocks of a single frame may read under the prefix-count
 // schedule before the single-frame heuristic takes taller bands.
 constexpr int64_t kPrefixCountPixels = 40 << 20;
+// Single frames of at most kMidFramePixels with one bin per lane (B <= 64)
+// take 32-column tiles and the tallest band that leaves at least
+// kMidFrameWaves work items of at most kMidFrameItemBytes output each, under
+// prefix counts while those read at most kMidPrefixPixels.
+constexpr int64_t kMidFramePixels = 1920 * 1080;
+constexpr int64_t kMidFrameWaves = 450;
+constexpr int64_t kMidFrameItemBytes = 640 << 10;
+constexpr int64_t kMidPrefixPixels = 20 << 20;
 
 // Scratch layout (uint32 words) for one frame:
 //   cnt    [kCounterWords]  fused schedule: arrivals per tile column (nTX), then
