@@ -54,6 +54,13 @@ __device__ __forceinline__ uint32_t left_carry(const FrameArgs& f, size_t e)
     return gmem(f.rowc)[e];
 }
 
+// Entry e of a frame's column carries (uint16 or uint32 by the frame's CC16).
+__device__ __forceinline__ uint32_t top_carry(const FrameArgs& f, size_t e)
+{
+    if (f.g.CC16) return gmem(reinterpret_cast<const uint16_t*>(f.colc))[e];
+    return gmem(f.colc)[e];
+}
+
 // Largest job whose `begin` is <= idx (jobs sorted by begin, jobs[0].begin == 0).
 // idx is uniform across the caller's wave, so the loads stay scalar.
 __device__ __forceinline__ int find_job(const IH_CONST Job* jobs, int32_t njobs, int64_t idx)

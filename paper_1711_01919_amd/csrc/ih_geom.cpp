@@ -14,7 +14,9 @@ ScratchLayout scratch_layout(const Geom& g)
     const size_t rowc_entries = (size_t)g.H * g.nTX * g.B;
     const size_t rowc_words = g.RC16 ? (rowc_entries + 1) / 2 : rowc_entries;
     s.colc = s.rowc + (rowc_words + 63) / 64 * 64;
-    s.corner = s.colc + bands * g.W * g.B;
+    const size_t colc_entries = bands * g.W * g.B;
+    const size_t colc_words = g.CC16 ? (colc_entries + 1) / 2 : colc_entries;
+    s.corner = s.colc + (colc_words + 63) / 64 * 64;
     s.words = s.corner + bands * g.nTX * g.B;
     return s;
 }
@@ -68,6 +70,7 @@ Geom make_geom(int32_t H, int32_t W, int32_t B, const TileChoice& t)
     g.CPL = t.bm_cpl;
     g.RC16 = W <= 65536 ? 1 : 0;
     g.K = t.K > 0 && !t.prefix ? t.K : 0;
+    g.CC16 = g.K == 0 && H <= 65536 ? 1 : 0;
     g.nS = g.K ? (g.nTY + g.K - 1) / g.K : 0;
     return g;
 }

@@ -38,6 +38,8 @@ struct Geom {
     int32_t PC;              // 1: prefix-count schedule (then K == 0)
     int32_t CPL;             // bin-major tile pass: columns per lane (1 or 4); 0 for H x W x B frames
     int32_t RC16;            // 1: left carries stored as uint16 (W <= 65536, so every one is below 2^16)
+    int32_t CC16;            // 1: column carries (colc) stored as uint16: reduce-then-scan or prefix
+                             // counts with H <= 65536, so every count and top carry is below 2^16
 };
 
 // Arrival counters of the fused schedule sit in the first kCounterWords words
@@ -73,7 +75,7 @@ constexpr int64_t kMidPrefixPixels = 20 << 20;
 //                           (segment-major, so a tile's rows are one contiguous run);
 //                           uint16 when RC16 (half the bytes the tile pass reads
 //                           beside its write stream), else uint32
-//   reduce-then-scan:
+//   reduce-then-scan (colc uint16 when CC16, else uint32):
 //   colc   [nTY][W][B]      column counts per tile band, scanned to top carries
 //   corner [nTY][nTX][B]    per-tile totals, scanned to top-left corner counts
 //   prefix counts:

@@ -260,8 +260,13 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     __syncthreads();
     count_rows<TX>(f, lutw, colh, ya, yb, x0, tw);
     __syncthreads();
-    for (int e = tid; e < tw * B; e += kAggThreads)
-        gmem(f.colc)[((size_t)i * g.W + x0) * B + e] = lds_get16(colh, (uint32_t)e);
+    const size_t cbase = ((size_t)i * g.W + x0) * B;
+    if (g.CC16) {
+        IH_GLOBAL uint16_t* cp = gmem(reinterpret_cast<uint16_t*>(f.colc)) + cbase;
+        for (int e = tid; e < tw * B; e += kAggThreads) cp[e] = (uint16_t)lds_get16(colh, (uint32_t)e);
+    } else {
+        for (int e = tid; e < tw * B; e += kAggThreads) gmem(f.colc)[cbase + e] = lds_get16(colh, (uint32_t)e);
+    }
     for (int b = tid; b < B; b += kAggThreads) {
         uint32_t s = 0;
         for (int x = 0; x < tw; ++x) s += lds_get16(colh, (uint32_t)(x * B + b));
@@ -272,7 +277,8 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
 // Exclusive scan of p[0], p[stride], ... p[(len-1)*stride] in place, starting
 // from `run`.  Loads of a chunk are issued before its stores so that many are
 // in flight at once.
-__device__ __forceinline__ void scan_seq(IH_GLOBAL uint32_t* p, int64_t stride, int len, uint32_t run)
+template <typename T>
+__device__ __forceinline__ void scan_seq(IH_GLOBAL T* p, int64_t stride, int len, uint32_t run)
 {
     // chunks of C elements, the last one masked: all loads of a chunk go out
     // before any of its stores (a store may alias a later load as far as the
@@ -284,13 +290,14 @@ __device__ __forceinline__ void scan_seq(IH_GLOBAL uint32_t* p, int64_t stride, 
         for (int u = 0; u < C; ++u) v[u] = k + u < len ? p[(k + u) * stride] : 0u;
 #pragma unroll
         for (int u = 0; u < C; ++u) {
-            if (k + u < len) p[(k + u) * stride] = run;
+            if (k + u < len) p[(k + u) * stride] = (T)run;
             run += v[u];
         }
     }
 }
 
-__device__ __forceinline__ uint32_t sum_seq(const IH_GLOBAL uint32_t* p, int64_t stride, int len)
+template <typename T>
+__device__ __forceinline__ uint32_t sum_seq(const IH_GLOBAL T* p, int64_t stride, int len)
 {
     constexpr int C = 16;
     uint32_t s = 0;
@@ -513,8 +520,8 @@ void count_batch_kernel(const FrameArgs* __restrict__ frames, const Job* __restr
 // the thread has no sequence but still takes part in the block's exchange
 // (every thread of a block sees the same len).  `stride` is the same for the
 // whole block, so address arithmetic stays scalar.
-template <int P>
-__device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t stride, int len, bool active,
+template <int P, typename T = uint32_t>
+__device__ __forceinline__ void scan_seq_parts(IH_GLOBAL T* p, int64_t stride, int len, bool active,
                                                uint32_t* sums)
 {
     if constexpr (P == 1) {
@@ -546,7 +553,7 @@ __device__ __forceinline__ void scan_seq_parts(IH_GLOBAL uint32_t* p, int64_t st
 #pragma unroll
         for (int u = 0; u < C; ++u)
             if (lo + u < hi) {
-                p[(int64_t)(lo + u) * stride] = run;
+                p[(int64_t)(lo + u) * stride] = (T)run;
                 run += v[u];
             }
     } else {
@@ -606,7 +613,10 @@ __device__ __forceinline__ void scan_body(const FrameArgs& f, int64_t blk, uint3
         return;
     }
     const int64_t t = blk * per + (int)threadIdx.x % per;
-    scan_seq_parts<P>(gmem(f.colc) + t, (int64_t)g.W * B, g.nTY, t < ncol, sums);
+    if (g.CC16)
+        scan_seq_parts<P>(gmem(reinterpret_cast<uint16_t*>(f.colc)) + t, (int64_t)g.W * B, g.nTY, t < ncol, sums);
+    else
+        scan_seq_parts<P>(gmem(f.colc) + t, (int64_t)g.W * B, g.nTY, t < ncol, sums);
 }
 
 template <int P>
@@ -758,14 +768,14 @@ __device__ __forceinline__ void tile_bm_body(const FrameArgs& f, int64_t item)
     uint32_t V[BG][CPL];
     {
         const IH_GLOBAL uint32_t* cp = gmem(f.corner) + ((size_t)i * g.nTX + j) * B + b_lo;
-        const IH_GLOBAL uint32_t* tp = gmem(f.colc) + ((size_t)i * W + xl) * B + b_lo;
+        const size_t tbase = ((size_t)i * W + xl) * B + b_lo;
         const uint32_t corner = lane < BG ? cp[lane] : 0u;     // lane t: corner of bin b_lo + t
 #pragma unroll
         for (int t = 0; t < BG; ++t) {
             uint32_t top[CPL], sum = 0;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                top[c] = c < nvalid ? tp[(size_t)c * B + t] : 0u;
+                top[c] = c < nvalid ? top_carry(f, tbase + (size_t)c * B + t) : 0u;
                 sum += top[c];
             }
             uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)corner, t) + wave_inclusive_sum(sum, lane) - sum;

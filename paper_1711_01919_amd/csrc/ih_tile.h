@@ -217,23 +217,35 @@ __device__ __forceinline__ void tile_body(const FrameArgs& f, int i, int jg, int
         uint32_t acc[BPL];
         const IH_GLOBAL uint32_t* corner = gmem(f.corner);
         const IH_GLOBAL uint32_t* colc = gmem(f.colc);
-        const IH_GLOBAL uint32_t* tp;
+        size_t tofs;
         const IH_GLOBAL uint32_t* tq = nullptr;
         const int K = g.K, I = K ? i / K : 0, k_in = i - I * K;
         if (g.PC || K == 0) {
-            tp = colc + ((size_t)i * g.W + x0) * B + b0;
+            tofs = ((size_t)i * g.W + x0) * B + b0;
         } else {
-            tp = colc + (((size_t)I * K + K - 1) * g.W + x0) * B + b0;
+            tofs = (((size_t)I * K + K - 1) * g.W + x0) * B + b0;
             if (k_in > 0) tq = colc + (((size_t)I * K + k_in - 1) * g.W + x0) * B + b0;
         }
+        if (g.CC16) {
+            const IH_GLOBAL uint16_t* c16 = gmem(reinterpret_cast<const uint16_t*>(f.colc));
 #pragma unroll
-        for (int k = 0; k < TX; ++k)
+            for (int k = 0; k < TX; ++k)
 #pragma unroll
-            for (int t = 0; t < BPL; ++t) {
-                const bool ok = k < ncols && bvalid[t];
-                const uint32_t v = *(ok ? tp + (size_t)k * B + t : colc);
-                V[t][k] = ok ? v : 0u;
-            }
+                for (int t = 0; t < BPL; ++t) {
+                    const bool ok = k < ncols && bvalid[t];
+                    const uint32_t v = *(ok ? c16 + tofs + (size_t)k * B + t : c16);
+                    V[t][k] = ok ? v : 0u;
+                }
+        } else {
+#pragma unroll
+            for (int k = 0; k < TX; ++k)
+#pragma unroll
+                for (int t = 0; t < BPL; ++t) {
+                    const bool ok = k < ncols && bvalid[t];
+                    const uint32_t v = *(ok ? colc + tofs + (size_t)k * B + t : colc);
+                    V[t][k] = ok ? v : 0u;
+                }
+        }
         if (tq) {
 #pragma unroll
             for (int k = 0; k < TX; ++k)
