@@ -64,6 +64,46 @@ __device__ __forceinline__ void wave_sync()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// The running counts of a row-carry wave over ns segments of a chunk, for
+// the lane's 2 <= bpl <= 4 bins: segment by segment, the counters of all of
+// the lane's bins are read from LDS together, then stored together (a wave's
+// stores of one segment and row are one contiguous run; storing bin by bin
+// over all segments instead would leave half-written lines to be written
+// back twice).
+__device__ __forceinline__ void rowcarry_walk(const FrameArgs& f, const uint32_t* lds, int lane, int bpl, int j0,
+                                              int ns, size_t row_off, size_t seg_stride, uint32_t (&run)[4])
+{
+    constexpr int G = 1;                 // segments per LDS round (register budget)
+    const Geom& g = f.g;
+    const int B = g.B;
+#pragma unroll 1
+    for (int s0 = 0; s0 < ns; s0 += G) {
+        uint32_t c[G][4];
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int b = lane * bpl + t;
+                const bool ok = t < bpl && b < B && s0 + u < ns;
+                const uint32_t v = lds_get8(lds, ok ? (uint32_t)((s0 + u) * B + b) : 0u);
+                c[u][t] = ok ? v : 0u;
+            }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            if (s0 + u >= ns) break;
+            const size_t o = row_off + (size_t)(j0 + s0 + u) * seg_stride + (size_t)lane * bpl;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t < bpl && lane * bpl + t < B) {
+                    if (g.RC16) gmem(reinterpret_cast<uint16_t*>(f.rowc))[o + t] = (uint16_t)run[t];
+                    else gmem(f.rowc)[o + t] = run[t];
+                }
+                run[t] += c[u][t];
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uint32_t* lds)
 {
     const Geom& g = f.g;
@@ -120,33 +160,34 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
             }
         }
         wave_sync();
-        // Per bin of the lane: the counters of four segments at a time are
-        // read from LDS together, then the running counts are stored
-        // segment by segment.
-        for (int t = 0; t < bpl; ++t) {
-            const int b = lane * bpl + t;
-            if (b >= B) break;
-            uint32_t r = run[t];
+        if (bpl == 1) {
+            // one bin per lane: four segments at a time
+            const int b = lane;
+            if (b < B) {
+                uint32_t r = run[0];
 #pragma unroll 1
-            for (int s0 = 0; s0 < ns; s0 += 4) {
-                uint32_t c[4];
+                for (int s0 = 0; s0 < ns; s0 += 4) {
+                    uint32_t c[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool ok = s0 + u < ns;
-                    const uint32_t v = lds_get8(lds, ok ? (uint32_t)((s0 + u) * B + b) : 0u);
-                    c[u] = ok ? v : 0u;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (s0 + u < ns) {
-                        const size_t o = row_off + (size_t)(j0 + s0 + u) * seg_stride + b;
-                        if (g.RC16) gmem(reinterpret_cast<uint16_t*>(f.rowc))[o] = (uint16_t)r;
-                        else gmem(f.rowc)[o] = r;
+                    for (int u = 0; u < 4; ++u) {
+                        const bool ok = s0 + u < ns;
+                        const uint32_t v = lds_get8(lds, ok ? (uint32_t)((s0 + u) * B + b) : 0u);
+                        c[u] = ok ? v : 0u;
                     }
-                    r += c[u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (s0 + u < ns) {
+                            const size_t o = row_off + (size_t)(j0 + s0 + u) * seg_stride + b;
+                            if (g.RC16) gmem(reinterpret_cast<uint16_t*>(f.rowc))[o] = (uint16_t)r;
+                            else gmem(f.rowc)[o] = r;
+                        }
+                        r += c[u];
+                    }
                 }
+                run[0] = r;
             }
-            run[t] = r;
+        } else {
+            rowcarry_walk(f, lds, lane, bpl, j0, ns, row_off, seg_stride, run);
         }
         wave_sync();
     }
