@@ -43,31 +43,31 @@ HBM_PEAK_GBS = 8000.0
 # any other combination reports null.
 TRAFFIC_RECORDS = {
     "uneven_batch_256": {
-        "kernel_sources_sha256": "fd455b062b9065ee89c1965c55b52c5af839869a7adb156693a7250a16aec620",
+        "kernel_sources_sha256": "8815988ea8a3cffc382233683cff62f5b258e04de9eb4fb50287cb8026d5ed65",
         "schedule": {
-            "1080x1920 B128": "64x120 nt prefix counts",
+            "1080x1920 B128": "64x120 nt reduce-then-scan",
             "1080x1920 B16": "32x120 reduce-then-scan",
-            "1080x1920 B32": "64x120 reduce-then-scan",
+            "1080x1920 B32": "64x120 nt reduce-then-scan",
             "1080x1920 B64": "64x120 nt reduce-then-scan",
             "2160x3840 B128": "64x128 reduce-then-scan",
             "2160x3840 B16": "64x128 reduce-then-scan",
-            "2160x3840 B32": "64x240 reduce-then-scan",
+            "2160x3840 B32": "64x240 nt reduce-then-scan",
             "2160x3840 B64": "128x240 reduce-then-scan",
             "240x320 B128": "32x60 nt prefix counts",
-            "240x320 B16": "32x8 nt prefix counts",
+            "240x320 B16": "32x16 nt prefix counts",
             "240x320 B32": "32x30 prefix counts",
             "240x320 B64": "32x30 nt prefix counts",
-            "480x640 B128": "64x120 nt prefix counts",
+            "480x640 B128": "32x240 nt prefix counts",
             "480x640 B16": "32x60 prefix counts",
             "480x640 B32": "32x60 prefix counts",
             "480x640 B64": "32x120 nt prefix counts",
-            "720x1280 B128": "32x240 reduce-then-scan",
-            "720x1280 B16": "64x60 reduce-then-scan",
+            "720x1280 B128": "64x240 nt prefix counts",
+            "720x1280 B16": "32x120 nt prefix counts",
             "720x1280 B32": "32x240 nt prefix counts",
             "720x1280 B64": "64x240 nt reduce-then-scan"
         },
-        "fetch_bytes": 2661279386,
-        "write_bytes": 126777794336,
+        "fetch_bytes": 2239122749,
+        "write_bytes": 126812773152,
         "source": "profiles/uneven_batch_256_tile_pass_hbm_counters.md"
     }
 }
