@@ -78,6 +78,29 @@ def test_wide_frames_left_carry_widths(ihb, orc, H, W, B):
     assert np.array_equal(ihb.compute_lut(f, B, lut).cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("H,W,B", [(65536, 8, 1), (65537, 8, 1), (70001, 24, 3)])
+def test_tall_frames_column_carry_widths(ihb, orc, H, W, B):
+    """Column carries are kept as uint16 up to 65536 rows (the largest top
+    carry, above the last band of a B=1 frame, is below 65536) and as uint32
+    beyond: the single-frame forms and a reduce-then-scan plan equal the
+    oracle on both sides of the boundary."""
+    rng = np.random.default_rng(H + W * 13 + B)
+    I = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    if B == 1:
+        I[:] = 77                           # every pixel in the one bin: carries as large as they get
+    want = orc.integral_histogram(I, B)
+    f = torch.from_numpy(I).cuda()
+    assert np.array_equal(ihb.compute(f, B).cpu().numpy(), want)
+    bm = ihb.compute_binmajor(f, B)
+    assert np.array_equal(bm.permute(1, 2, 0).contiguous().cpu().numpy(), want)
+    out = torch.empty((H, W, B), dtype=torch.uint32, device="cuda")
+    plan = ihb.BatchPlan([f], [out], [B], tile=(32, 64), carry_bands=0)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    plan.close()
+
+
 def test_unaligned_frame_and_output(ihb, orc):
     """Frame and output views that start off a 16-byte boundary take the
     guarded kernel and must give the same bits."""
