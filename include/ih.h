@@ -126,7 +126,8 @@ ih_status ih_compute_lut(const uint8_t* frame, int32_t H, int32_t W, int32_t B, 
  * frame's carries exceed the array.  Every frame of at most 3840 x 2160
  * pixels fits at B <= 128, and every frame of at most 7680 x 4320 pixels at
  * B <= 32; beyond that it depends on the tile ih_compute picks (1920 x 1080
- * at B = 256 fits, 3840 x 2160 at B = 256 and 7680 x 4320 at B = 64 do not).
+ * at B = 256 and 7680 x 4320 at B = 64 fit, 3840 x 2160 at B = 256 and
+ * 7680 x 4320 at B = 128 do not).
  */
 #define IH_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 ih_status ih_compute_noalloc(const uint8_t* frame, int32_t H, int32_t W, int32_t B, uint32_t* out,

@@ -121,15 +121,28 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B)
         if (t.prefix && !prefix_supported(make_geom(H, W, B, t))) t.prefix = false;
         return t;
     }
+    // Tallest tile (fewest carries) that still gives enough independent
+    // waves (one per work item in a single-frame launch).  Frames above
+    // 1920 x 1080 and up to 3840 x 2160 with B <= 128 take non-temporal
+    // stores and at least about
+    // 480 waves (3840 x 2160 B=16 / 32 / 64 / 128: 140 / 214 / 413 / 785 us
+    // against 147 / 237 / 451 / 860 us with regular stores and about 1000
+    // waves); larger ones about 1000 waves and regular stores (7680 x 4320
+    // B=16 took 774 us with non-temporal stores against 492 us).  B=64 takes
+    // 128-column tiles, and beyond 3840 x 2160 bands of at most 256 rows
+    // (7680 x 4320 B=64: 1.66 ms at 128 x 256 against 2.16 ms at 64 x 512;
+    // 8192 x 8192 B=64: 3.18 against 3.48 ms).
+    const bool upto4k = bins_per_lane(B) <= 2 && (int64_t)H * W > kMidFramePixels && (int64_t)H * W <= k4KFramePixels;
+    const int64_t min_waves = upto4k ? kMinWaves4K : kMinWaves;
+    auto waves = [&](int tx, int ty) {
+        return (int64_t)((H + ty - 1) / ty) * make_geom(H, W, B, TileChoice{tx, 1, false}).nJG;
+    };
     t.TX = bins_per_lane(B) == 4 ? 32 : 64;
-    // Tallest tile (fewest carries) that still gives about 1000 independent
-    // waves (one per work item in a single-frame launch): measured best for
-    // 1080p to 8K frames at B = 16 to 64, against both half and twice that.
-    constexpr int64_t kMinWaves = 960;
-    const Geom g0 = make_geom(H, W, B, TileChoice{t.TX, 1, false});
-    int TY = 512;
-    while (TY > 16 && (int64_t)((H + TY - 1) / TY) * g0.nJG < kMinWaves) TY /= 2;
+    if (B == 64 && waves(128, 16) >= min_waves) t.TX = 128;
+    int TY = (t.TX == 128 && !upto4k) ? 256 : 512;
+    while (TY > 16 && waves(t.TX, TY) < min_waves) TY /= 2;
     t.TY = TY;
+    t.nontemporal = upto4k && waves(t.TX, TY) >= min_waves;
     // Small frames (too few waves even at 16 rows): 32-column tiles for
     // parallelism and the prefix-count schedule (two launches, no scans;
     // 640 x 480 B=32: 25.0 against 29.0 us per frame under reduce-then-scan
@@ -138,9 +151,10 @@ TileChoice default_tile(int32_t H, int32_t W, int32_t B)
     // kMaxPrefixBands of them and that stays within kPrefixCountPixels
     // (1920 x 1080 B=16: 32-row bands, 70.6 us against 107 us at 8 rows and
     // 150 us under reduce-then-scan).
-    if ((int64_t)((H + TY - 1) / TY) * g0.nJG < kMinWaves) {
+    if (waves(t.TX, TY) < min_waves) {
         t.TX = 32;
         t.TY = 8;
+        t.nontemporal = false;
         auto bands = [&](int ty) { return (H + ty - 1) / ty; };
         while (t.TY < 64 && (bands(t.TY) > kMaxPrefixBands || (int64_t)H * W * bands(t.TY) / 2 > kPrefixCountPixels))
             t.TY *= 2;

@@ -67,6 +67,12 @@ constexpr int64_t kMidFramePixels = 1920 * 1080;
 constexpr int64_t kMidFrameWaves = 450;
 constexpr int64_t kMidFrameItemBytes = 640 << 10;
 constexpr int64_t kMidPrefixPixels = 20 << 20;
+// Other single frames: about kMinWaves work items, or kMinWaves4K for frames
+// above kMidFramePixels and of at most k4KFramePixels with B <= 128 (which
+// take non-temporal stores).
+constexpr int64_t kMinWaves = 960;
+constexpr int64_t kMinWaves4K = 480;
+constexpr int64_t k4KFramePixels = 3840 * 2160;
 
 // Scratch layout (uint32 words) for one frame:
 //   cnt    [kCounterWords]  fused schedule: arrivals per tile column (nTX), then

@@ -75,7 +75,7 @@ def test_compute_noalloc_rejects_before_touching_the_device(lib):
     assert f(fake, 4, 4, 8, fake + 2, None) == 1
     assert f(fake, 65536, 65536, 8, fake, None) == 2           # H*W = 2^32
     assert f(fake, 2160, 3840, 256, fake, None) == 2           # carries beyond the array
-    assert f(fake, 4320, 7680, 64, fake, None) == 2
+    assert f(fake, 4320, 7680, 128, fake, None) == 2
 
 
 class View(ctypes.Structure):

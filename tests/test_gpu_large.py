@@ -100,6 +100,20 @@ def test_index_boundary_2_32_entries(ihb, orc, rows_compare):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("B", [16, 64, 128])
+def test_single_4k_frames(ihb, orc, rows_compare, B):
+    """One 3840x2160 frame through ih_compute (non-temporal stores; 64-column
+    tiles, 128-column at B=64); every entry against the oracle."""
+    rng = np.random.default_rng(20 + B)
+    I = rng.integers(0, 256, size=(2160, 3840), dtype=np.uint8)
+    out = ihb.compute(torch.from_numpy(I).cuda(), B)
+    torch.cuda.synchronize()
+    diff = rows_compare(orc, out, I, B)
+    assert diff is None, diff
+    del out
+    torch.cuda.empty_cache()
+
+
 def test_batched_large_frames(ihb, orc, rows_compare):
     """Two 3840x2160 frames of different bin counts in one batched plan, with
     the autotuner on; every entry against the oracle."""

@@ -56,8 +56,8 @@ def test_noalloc_matches_compute_twice(ihb, orc, first, second):
 
 def test_noalloc_rejects_frames_beyond_its_array(ihb):
     """Frames whose carries exceed the array (3840x2160 at B=256, 7680x4320
-    at B=64): an error, nothing written."""
-    for H, W, B in ((2160, 3840, 256), (4320, 7680, 64)):
+    at B=128): an error, nothing written."""
+    for H, W, B in ((2160, 3840, 256), (4320, 7680, 128)):
         f = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
         out = torch.full((4,), 7, dtype=torch.uint32, device="cuda")
         st = ihb.lib.ih_compute_noalloc(ctypes.c_void_p(f.data_ptr()), H, W, B, ctypes.c_void_p(out.data_ptr()),
