@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # any other combination reports null.
 TRAFFIC_RECORDS = {
     "uneven_batch_256": {
-        "kernel_sources_sha256": "8815988ea8a3cffc382233683cff62f5b258e04de9eb4fb50287cb8026d5ed65",
+        "kernel_sources_sha256": "dfe302fae5b6bd7654711fe13b55c476e0407fd0ae6fb1b192e2491ef097628c",
         "schedule": {
             "1080x1920 B128": "64x120 nt reduce-then-scan",
             "1080x1920 B16": "32x120 reduce-then-scan",
@@ -61,13 +61,13 @@ TRAFFIC_RECORDS = {
             "480x640 B16": "32x60 prefix counts",
             "480x640 B32": "32x60 prefix counts",
             "480x640 B64": "32x120 nt prefix counts",
-            "720x1280 B128": "64x240 nt prefix counts",
-            "720x1280 B16": "32x120 nt prefix counts",
+            "720x1280 B128": "32x240 prefix counts",
+            "720x1280 B16": "32x120 nt reduce-then-scan",
             "720x1280 B32": "32x240 nt prefix counts",
             "720x1280 B64": "64x240 nt reduce-then-scan"
         },
-        "fetch_bytes": 2239122749,
-        "write_bytes": 126812773152,
+        "fetch_bytes": 2269494880,
+        "write_bytes": 126811569696,
         "source": "profiles/uneven_batch_256_tile_pass_hbm_counters.md"
     }
 }
