@@ -666,7 +666,7 @@ def run_legs(torch, ihb, synth, stream, args, want, legs) -> None:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 
