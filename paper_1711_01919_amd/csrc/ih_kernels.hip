@@ -73,33 +73,26 @@ __device__ __forceinline__ void wave_sync()
 __device__ __forceinline__ void rowcarry_walk(const FrameArgs& f, const uint32_t* lds, int lane, int bpl, int j0,
                                               int ns, size_t row_off, size_t seg_stride, uint32_t (&run)[4])
 {
-    constexpr int G = 1;                 // segments per LDS round (register budget)
     const Geom& g = f.g;
     const int B = g.B;
 #pragma unroll 1
-    for (int s0 = 0; s0 < ns; s0 += G) {
-        uint32_t c[G][4];
+    for (int sg = 0; sg < ns; ++sg) {
+        uint32_t c[4];
 #pragma unroll
-        for (int u = 0; u < G; ++u)
+        for (int t = 0; t < 4; ++t) {
+            const int b = lane * bpl + t;
+            const bool ok = t < bpl && b < B;
+            const uint32_t v = lds_get8(lds, ok ? (uint32_t)(sg * B + b) : 0u);
+            c[t] = ok ? v : 0u;
+        }
+        const size_t o = row_off + (size_t)(j0 + sg) * seg_stride + (size_t)lane * bpl;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int b = lane * bpl + t;
-                const bool ok = t < bpl && b < B && s0 + u < ns;
-                const uint32_t v = lds_get8(lds, ok ? (uint32_t)((s0 + u) * B + b) : 0u);
-                c[u][t] = ok ? v : 0u;
+        for (int t = 0; t < 4; ++t) {
+            if (t < bpl && lane * bpl + t < B) {
+                if (g.RC16) gmem(reinterpret_cast<uint16_t*>(f.rowc))[o + t] = (uint16_t)run[t];
+                else gmem(f.rowc)[o + t] = run[t];
             }
-#pragma unroll
-        for (int u = 0; u < G; ++u) {
-            if (s0 + u >= ns) break;
-            const size_t o = row_off + (size_t)(j0 + s0 + u) * seg_stride + (size_t)lane * bpl;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (t < bpl && lane * bpl + t < B) {
-                    if (g.RC16) gmem(reinterpret_cast<uint16_t*>(f.rowc))[o + t] = (uint16_t)run[t];
-                    else gmem(f.rowc)[o + t] = run[t];
-                }
-                run[t] += c[u][t];
-            }
+            run[t] += c[t];
         }
     }
 }
@@ -208,15 +201,18 @@ __host__ __device__ inline size_t rowcarry_lds_bytes(const Geom& g)
 // (16-bit LDS counters, <= TY pixels each), written to colc[i][x][b], and the
 // tile's total per bin, written to corner[i][j][b].
 
-// Two 16-bit counters per LDS word: column counts are <= TY <= 65535, so a
-// carry never crosses halves.
-__device__ __forceinline__ void lds_inc16(uint32_t* h, uint32_t e)
+// Two 16-bit counters per LDS word (bins b and b ^ 1 of a column): column
+// counts are <= 65535, so a carry never crosses halves.  A column takes
+// col_words(B) words, one more than its counters need, so that the words of
+// neighbouring columns start on different LDS banks.
+__host__ __device__ inline int col_words(int B) { return (B + 1) / 2 + 1; }
+__device__ __forceinline__ void col_inc(uint32_t* h, int cw, int x, uint32_t b)
 {
-    atomicAdd(&h[e >> 1], 1u << ((e & 1u) << 4));
+    atomicAdd(&h[x * cw + (int)(b >> 1)], 1u << ((b & 1u) << 4));
 }
-__device__ __forceinline__ uint32_t lds_get16(const uint32_t* h, uint32_t e)
+__device__ __forceinline__ uint32_t col_get(const uint32_t* h, int cw, int x, int b)
 {
-    return (h[e >> 1] >> ((e & 1u) << 4)) & 0xFFFFu;
+    return (h[x * cw + (b >> 1)] >> ((b & 1) << 4)) & 0xFFFFu;
 }
 
 // Pixels of rows [ya, yb) and columns [x0, x0 + tw) added to the per-column
@@ -230,6 +226,7 @@ __device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* l
                                            int x0, int tw)
 {
     const Geom& g = f.g;
+    const int cw = col_words(g.B);
     if ((g.W % 4) == 0 && (reinterpret_cast<uintptr_t>(f.frame) & 3) == 0) {
         constexpr int TPR = TX / 4;                    // threads per row
         constexpr int kRowsPerPass4 = kAggThreads / TPR;
@@ -252,8 +249,7 @@ __device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* l
                 if (r0 + u * kRowsPerPass4 < th)
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
-                        lds_inc16(colh, (uint32_t)((4 * tq + c) * g.B) +
-                                            bin_of(f, lutw, (v[u] >> (8 * c)) & 0xFFu, (uint32_t)g.B));
+                        col_inc(colh, cw, 4 * tq + c, bin_of(f, lutw, (v[u] >> (8 * c)) & 0xFFu, (uint32_t)g.B));
         }
         return;
     }
@@ -273,7 +269,7 @@ __device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* l
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (r0 + u * kRowsPerPass < th)
-                lds_inc16(colh, (uint32_t)(tx * g.B) + bin_of(f, lutw, v[u], (uint32_t)g.B));
+                col_inc(colh, cw, tx, bin_of(f, lutw, v[u], (uint32_t)g.B));
     }
 }
 
@@ -296,21 +292,22 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     const int yb = g.PC ? y0 : min(g.H, y0 + g.TY);
     const int tid = threadIdx.x;
 
-    for (int e = tid; e < (TX * B + 1) / 2; e += kAggThreads) colh[e] = 0;
+    const int cw = col_words(B);
+    for (int e = tid; e < TX * cw; e += kAggThreads) colh[e] = 0;
     stage_lut(f, lutw, tid, kAggThreads);
     __syncthreads();
     count_rows<TX>(f, lutw, colh, ya, yb, x0, tw);
     __syncthreads();
     const size_t cbase = ((size_t)i * g.W + x0) * B;
-    if (g.CC16) {
-        IH_GLOBAL uint16_t* cp = gmem(reinterpret_cast<uint16_t*>(f.colc)) + cbase;
-        for (int e = tid; e < tw * B; e += kAggThreads) cp[e] = (uint16_t)lds_get16(colh, (uint32_t)e);
-    } else {
-        for (int e = tid; e < tw * B; e += kAggThreads) gmem(f.colc)[cbase + e] = lds_get16(colh, (uint32_t)e);
+    for (int e = tid; e < tw * B; e += kAggThreads) {
+        const int x = e / B, b = e - x * B;
+        const uint32_t v = col_get(colh, cw, x, b);
+        if (g.CC16) gmem(reinterpret_cast<uint16_t*>(f.colc))[cbase + e] = (uint16_t)v;
+        else gmem(f.colc)[cbase + e] = v;
     }
     for (int b = tid; b < B; b += kAggThreads) {
         uint32_t s = 0;
-        for (int x = 0; x < tw; ++x) s += lds_get16(colh, (uint32_t)(x * B + b));
+        for (int x = 0; x < tw; ++x) s += col_get(colh, cw, x, b);
         gmem(f.corner)[((size_t)i * g.nTX + j) * B + b] = s;
     }
 }
@@ -384,7 +381,8 @@ __device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, 
     IH_GLOBAL uint32_t* colc = gmem(f.colc);
     IH_GLOBAL uint32_t* corner = gmem(f.corner);
 
-    for (int e = tid; e < (TX * B + 1) / 2; e += kAggThreads) colh[e] = 0;
+    const int cw = col_words(B);
+    for (int e = tid; e < TX * cw; e += kAggThreads) colh[e] = 0;
     for (int b = tid; b < B; b += kAggThreads) tot[b] = 0;
     stage_lut(f, lutw, tid, kAggThreads);
     __syncthreads();
@@ -415,7 +413,7 @@ __device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, 
 #pragma unroll
                 for (int u = 0; u < kPre; ++u) {
                     const int r = Ys + tr + u * kRowsPerPass;
-                    if (r >= ya && r < min(Ye, ya + g.TY)) lds_inc16(colh, (uint32_t)(tx * B) + q[u]);
+                    if (r >= ya && r < min(Ye, ya + g.TY)) col_inc(colh, cw, tx, q[u]);
                 }
             }
         } else {
@@ -430,16 +428,18 @@ __device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, 
             // every element a thread takes is of bin tid % B
             uint32_t part = 0;
             for (int e = tid; e < tw * B; e += kAggThreads) {
-                const uint32_t v = lds_get16(colh, (uint32_t)e);
+                const int x = e / B;
+                const uint32_t v = col_get(colh, cw, x, e - x * B);
                 cdst[e] = v;
                 part += v;
             }
             if (tid < tw * B) atomicAdd(&tot[tid % B], part);
         } else {
             for (int e = tid; e < tw * B; e += kAggThreads) {
-                const uint32_t v = lds_get16(colh, (uint32_t)e);
+                const int x = e / B;
+                const uint32_t v = col_get(colh, cw, x, e - x * B);
                 cdst[e] = v;
-                atomicAdd(&tot[e % B], v);
+                atomicAdd(&tot[e - x * B], v);
             }
         }
         __syncthreads();
@@ -496,7 +496,7 @@ constexpr int kRowsPerCountBlock = kAggThreads / kWave;
 // fused schedule B tile-column totals and two flags.
 __host__ __device__ inline size_t agg_lds_bytes(int TX, int B)
 {
-    return ((size_t)TX * B + 1) / 2 * 4 + 256 + (size_t)B * 4 + 8;
+    return (size_t)TX * col_words(B) * 4 + 256 + (size_t)B * 4 + 8;
 }
 
 // The tile-block role of the count launch, by schedule.  The fused
@@ -507,7 +507,7 @@ template <int TX, bool FUSED>
 __device__ __forceinline__ void agg_role(const FrameArgs& f, int64_t blk, uint32_t* lds)
 {
     uint32_t* colh = lds;
-    uint32_t* lutw = colh + ((size_t)TX * f.g.B + 1) / 2;
+    uint32_t* lutw = colh + (size_t)TX * col_words(f.g.B);
     if constexpr (FUSED) {
         uint32_t* tot = lutw + 64;
         agg_fused_body<TX>(f, blk, colh, lutw, tot, tot + f.g.B);
