@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # any other combination reports null.
 TRAFFIC_RECORDS = {
     "uneven_batch_256": {
-        "kernel_sources_sha256": "76df4de205c21c0b1628c85791700cbd984255d96341ee55e78d3bd3e54f53aa",
+        "kernel_sources_sha256": "8f4fe5c6096eb4eda0f76d9b496ad83a3a19538742540e23fddf072bc0eb1c3f",
         "schedule": {
             "1080x1920 B128": "64x120 nt reduce-then-scan",
             "1080x1920 B16": "32x120 reduce-then-scan",
@@ -51,7 +51,7 @@ TRAFFIC_RECORDS = {
             "1080x1920 B64": "64x120 nt reduce-then-scan",
             "2160x3840 B128": "64x128 reduce-then-scan",
             "2160x3840 B16": "64x128 reduce-then-scan",
-            "2160x3840 B32": "64x240 reduce-then-scan",
+            "2160x3840 B32": "64x240 nt reduce-then-scan",
             "2160x3840 B64": "128x240 reduce-then-scan",
             "240x320 B128": "32x60 nt prefix counts",
             "240x320 B16": "32x16 nt prefix counts",
@@ -61,13 +61,13 @@ TRAFFIC_RECORDS = {
             "480x640 B16": "32x60 prefix counts",
             "480x640 B32": "32x60 prefix counts",
             "480x640 B64": "32x120 nt prefix counts",
-            "720x1280 B128": "32x240 reduce-then-scan",
+            "720x1280 B128": "32x240 prefix counts",
             "720x1280 B16": "32x120 nt prefix counts",
-            "720x1280 B32": "32x240 nt prefix counts",
+            "720x1280 B32": "32x240 nt reduce-then-scan",
             "720x1280 B64": "64x240 nt reduce-then-scan"
         },
-        "fetch_bytes": 2266386710,
-        "write_bytes": 126793029024,
+        "fetch_bytes": 2268904034,
+        "write_bytes": 126806069856,
         "source": "profiles/uneven_batch_256_tile_pass_hbm_counters.md"
     }
 }

@@ -198,21 +198,54 @@ __host__ __device__ inline size_t rowcarry_lds_bytes(const Geom& g)
 // Phase 1b: per-tile column counts (agg)
 // ---------------------------------------------------------------------------
 // One 256-thread block per TY x TX tile: per-column bin counts of the tile
-// (16-bit LDS counters, <= TY pixels each), written to colc[i][x][b], and the
+// (LDS counters, <= TY pixels each), written to colc[i][x][b], and the
 // tile's total per bin, written to corner[i][j][b].
 
-// Two 16-bit counters per LDS word (bins b and b ^ 1 of a column): column
-// counts are <= 65535, so a carry never crosses halves.  A column takes
-// col_words(B) words, one more than its counters need, so that the words of
+// Column counters of a tile: one 32-bit word per bin where the tile's
+// counters fit kWideColWords words, else two 16-bit counters per word (bins b
+// and b ^ 1 of a column; column counts are <= 65535, so a carry never crosses
+// halves).  Separate words take fewer same-address collisions among the
+// lanes of one LDS increment, the packed form half the LDS of wide tiles with
+// many bins.  sh is 0 for the first form, 1 for the second.  A column takes
+// col_words words, one more than its counters need, so that the words of
 // neighbouring columns start on different LDS banks.
-__host__ __device__ inline int col_words(int B) { return (B + 1) / 2 + 1; }
-__device__ __forceinline__ void col_inc(uint32_t* h, int cw, int x, uint32_t b)
+constexpr int kWideColWords = 64 * 65;
+__host__ __device__ inline int col_shift(int TX, int B) { return TX * (B + 1) <= kWideColWords ? 0 : 1; }
+__host__ __device__ inline int col_words(int TX, int B) { return col_shift(TX, B) ? (B + 1) / 2 + 1 : B + 1; }
+__device__ __forceinline__ void col_inc(uint32_t* h, int cw, int sh, int x, uint32_t b)
 {
-    atomicAdd(&h[x * cw + (int)(b >> 1)], 1u << ((b & 1u) << 4));
+    atomicAdd(&h[x * cw + (int)(b >> sh)], 1u << ((b & (uint32_t)sh) << 4));
 }
-__device__ __forceinline__ uint32_t col_get(const uint32_t* h, int cw, int x, int b)
+template <int SH>
+__device__ __forceinline__ void col_inc(uint32_t* h, int cw, int sh, int x, uint32_t b)
 {
-    return (h[x * cw + (b >> 1)] >> ((b & 1) << 4)) & 0xFFFFu;
+    if constexpr (SH == 0) atomicAdd(&h[x * cw + (int)b], 1u);
+    else if constexpr (SH == 1) atomicAdd(&h[x * cw + (int)(b >> 1)], 1u << ((b & 1u) << 4));
+    else col_inc(h, cw, sh, x, b);
+}
+
+// Bin of byte c of a loaded word w: floor(v B / 256) (kBinScaled), the same
+// as one bit-field extract when B = 2^k with k >= 1 (kBinShift; bs = 8 - k,
+// so 8 c + bs <= 31), the bin table staged in LDS (kBinTable), or either of
+// the first and the last as the frame has it (kBinAny).
+enum BinForm { kBinScaled, kBinShift, kBinTable, kBinAny };
+template <int BF>
+__device__ __forceinline__ uint32_t bin_in_word(const FrameArgs& f, const uint32_t* lutw, uint32_t w, int c,
+                                                uint32_t B, int bs)
+{
+    if constexpr (BF == kBinShift) {
+        return (w >> (8 * c + bs)) & (B - 1u);
+    } else {
+        const uint32_t v = (w >> (8 * c)) & 0xFFu;
+        if constexpr (BF == kBinTable) return (lutw[v >> 2] >> (8 * (v & 3u))) & 0xFFu;
+        else if constexpr (BF == kBinScaled) return (v * B) >> 8;
+        else return bin_of(f, lutw, v, B);
+    }
+}
+__device__ __forceinline__ uint32_t col_get(const uint32_t* h, int cw, int sh, int x, int b)
+{
+    const uint32_t w = h[x * cw + (b >> sh)];
+    return sh ? (w >> ((b & 1) << 4)) & 0xFFFFu : w;
 }
 
 // Pixels of rows [ya, yb) and columns [x0, x0 + tw) added to the per-column
@@ -220,13 +253,16 @@ __device__ __forceinline__ uint32_t col_get(const uint32_t* h, int cw, int x, in
 // of 4, frame 4-byte aligned; tw is then a multiple of 4 too): thread tid
 // takes the four columns 4 (tid % (TX/4)) .. + 3 of every (kAggThreads /
 // (TX/4))-th row with one load.  Otherwise thread tid takes column tid % TX
-// of every (kAggThreads / TX)-th row.
-template <int TX>
-__device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* lutw, uint32_t* colh, int ya, int yb,
-                                           int x0, int tw)
+// of every (kAggThreads / TX)-th row.  Compiled per counter form (SH: 0 or
+// 1 as col_shift, -1 for the form given by sh) and bin form (BF), so that an
+// increment costs the fewest instructions.
+template <int TX, int SH, int BF>
+__device__ __forceinline__ void count_rows_as(const FrameArgs& f, const uint32_t* lutw, uint32_t* colh, int ya, int yb,
+                                              int x0, int tw, int sh, int bs)
 {
     const Geom& g = f.g;
-    const int cw = col_words(g.B);
+    const uint32_t B = (uint32_t)g.B;
+    const int cw = col_words(TX, g.B);
     if ((g.W % 4) == 0 && (reinterpret_cast<uintptr_t>(f.frame) & 3) == 0) {
         constexpr int TPR = TX / 4;                    // threads per row
         constexpr int kRowsPerPass4 = kAggThreads / TPR;
@@ -249,7 +285,7 @@ __device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* l
                 if (r0 + u * kRowsPerPass4 < th)
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
-                        col_inc(colh, cw, 4 * tq + c, bin_of(f, lutw, (v[u] >> (8 * c)) & 0xFFu, (uint32_t)g.B));
+                        col_inc<SH>(colh, cw, sh, 4 * tq + c, bin_in_word<BF>(f, lutw, v[u], c, B, bs));
         }
         return;
     }
@@ -269,7 +305,26 @@ __device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* l
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (r0 + u * kRowsPerPass < th)
-                col_inc(colh, cw, tx, bin_of(f, lutw, v[u], (uint32_t)g.B));
+                col_inc<SH>(colh, cw, sh, tx, bin_in_word<BF>(f, lutw, v[u], 0, B, bs));
+    }
+}
+
+template <int TX>
+__device__ __forceinline__ void count_rows(const FrameArgs& f, const uint32_t* lutw, uint32_t* colh, int ya, int yb,
+                                           int x0, int tw)
+{
+    const int B = f.g.B;
+    const int bs = 8 - (31 - __builtin_clz((uint32_t)B));
+    const bool wide = col_shift(TX, B) == 0;
+    if (f.lut) {
+        if (wide) count_rows_as<TX, 0, kBinTable>(f, lutw, colh, ya, yb, x0, tw, 0, bs);
+        else count_rows_as<TX, 1, kBinTable>(f, lutw, colh, ya, yb, x0, tw, 1, bs);
+    } else if (B >= 2 && (B & (B - 1)) == 0) {
+        if (wide) count_rows_as<TX, 0, kBinShift>(f, lutw, colh, ya, yb, x0, tw, 0, bs);
+        else count_rows_as<TX, 1, kBinShift>(f, lutw, colh, ya, yb, x0, tw, 1, bs);
+    } else {
+        if (wide) count_rows_as<TX, 0, kBinScaled>(f, lutw, colh, ya, yb, x0, tw, 0, bs);
+        else count_rows_as<TX, 1, kBinScaled>(f, lutw, colh, ya, yb, x0, tw, 1, bs);
     }
 }
 
@@ -292,7 +347,7 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     const int yb = g.PC ? y0 : min(g.H, y0 + g.TY);
     const int tid = threadIdx.x;
 
-    const int cw = col_words(B);
+    const int cw = col_words(TX, B), sh = col_shift(TX, B);
     for (int e = tid; e < TX * cw; e += kAggThreads) colh[e] = 0;
     stage_lut(f, lutw, tid, kAggThreads);
     __syncthreads();
@@ -301,13 +356,13 @@ __device__ __forceinline__ void agg_body(const FrameArgs& f, int64_t tile, uint3
     const size_t cbase = ((size_t)i * g.W + x0) * B;
     for (int e = tid; e < tw * B; e += kAggThreads) {
         const int x = e / B, b = e - x * B;
-        const uint32_t v = col_get(colh, cw, x, b);
+        const uint32_t v = col_get(colh, cw, sh, x, b);
         if (g.CC16) gmem(reinterpret_cast<uint16_t*>(f.colc))[cbase + e] = (uint16_t)v;
         else gmem(f.colc)[cbase + e] = v;
     }
     for (int b = tid; b < B; b += kAggThreads) {
         uint32_t s = 0;
-        for (int x = 0; x < tw; ++x) s += col_get(colh, cw, x, b);
+        for (int x = 0; x < tw; ++x) s += col_get(colh, cw, sh, x, b);
         gmem(f.corner)[((size_t)i * g.nTX + j) * B + b] = s;
     }
 }
@@ -381,7 +436,7 @@ __device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, 
     IH_GLOBAL uint32_t* colc = gmem(f.colc);
     IH_GLOBAL uint32_t* corner = gmem(f.corner);
 
-    const int cw = col_words(B);
+    const int cw = col_words(TX, B), sh = col_shift(TX, B);
     for (int e = tid; e < TX * cw; e += kAggThreads) colh[e] = 0;
     for (int b = tid; b < B; b += kAggThreads) tot[b] = 0;
     stage_lut(f, lutw, tid, kAggThreads);
@@ -413,11 +468,11 @@ __device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, 
 #pragma unroll
                 for (int u = 0; u < kPre; ++u) {
                     const int r = Ys + tr + u * kRowsPerPass;
-                    if (r >= ya && r < min(Ye, ya + g.TY)) col_inc(colh, cw, tx, q[u]);
+                    if (r >= ya && r < min(Ye, ya + g.TY)) col_inc(colh, cw, sh, tx, q[u]);
                 }
             }
         } else {
-            count_rows<TX>(f, lutw, colh, ya, min(Ye, ya + g.TY), x0, tw);
+            count_rows_as<TX, -1, kBinAny>(f, lutw, colh, ya, min(Ye, ya + g.TY), x0, tw, sh, 0);
         }
         __syncthreads();
         // snapshot k for tile band k + 1 of the carry band, the totals (K - 1) after the last
@@ -429,7 +484,7 @@ __device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, 
             uint32_t part = 0;
             for (int e = tid; e < tw * B; e += kAggThreads) {
                 const int x = e / B;
-                const uint32_t v = col_get(colh, cw, x, e - x * B);
+                const uint32_t v = col_get(colh, cw, sh, x, e - x * B);
                 cdst[e] = v;
                 part += v;
             }
@@ -437,7 +492,7 @@ __device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, 
         } else {
             for (int e = tid; e < tw * B; e += kAggThreads) {
                 const int x = e / B;
-                const uint32_t v = col_get(colh, cw, x, e - x * B);
+                const uint32_t v = col_get(colh, cw, sh, x, e - x * B);
                 cdst[e] = v;
                 atomicAdd(&tot[e - x * B], v);
             }
@@ -492,11 +547,11 @@ __device__ __forceinline__ void agg_fused_body(const FrameArgs& f, int64_t blk, 
 // holds its frame's row-block count, followed by the frame's tile blocks.
 constexpr int kRowsPerCountBlock = kAggThreads / kWave;
 
-// LDS of a tile block: 16-bit column counters, the bin table, and for the
+// LDS of a tile block: column counters, the bin table, and for the
 // fused schedule B tile-column totals and two flags.
 __host__ __device__ inline size_t agg_lds_bytes(int TX, int B)
 {
-    return (size_t)TX * col_words(B) * 4 + 256 + (size_t)B * 4 + 8;
+    return (size_t)TX * col_words(TX, B) * 4 + 256 + (size_t)B * 4 + 8;
 }
 
 // The tile-block role of the count launch, by schedule.  The fused
@@ -507,7 +562,7 @@ template <int TX, bool FUSED>
 __device__ __forceinline__ void agg_role(const FrameArgs& f, int64_t blk, uint32_t* lds)
 {
     uint32_t* colh = lds;
-    uint32_t* lutw = colh + (size_t)TX * col_words(f.g.B);
+    uint32_t* lutw = colh + (size_t)TX * col_words(TX, f.g.B);
     if constexpr (FUSED) {
         uint32_t* tot = lutw + 64;
         agg_fused_body<TX>(f, blk, colh, lutw, tot, tot + f.g.B);
