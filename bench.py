@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # any other combination reports null.
 TRAFFIC_RECORDS = {
     "uneven_batch_256": {
-        "kernel_sources_sha256": "8f4fe5c6096eb4eda0f76d9b496ad83a3a19538742540e23fddf072bc0eb1c3f",
+        "kernel_sources_sha256": "23c7a9c5a351e4e84255648fdd937497fa1b122128c17abc482c179daabb0cf6",
         "schedule": {
             "1080x1920 B128": "64x120 nt reduce-then-scan",
             "1080x1920 B16": "32x120 reduce-then-scan",
@@ -56,18 +56,18 @@ TRAFFIC_RECORDS = {
             "240x320 B128": "32x60 nt prefix counts",
             "240x320 B16": "32x16 nt prefix counts",
             "240x320 B32": "32x30 prefix counts",
-            "240x320 B64": "32x30 nt prefix counts",
+            "240x320 B64": "32x30 prefix counts",
             "480x640 B128": "32x240 nt prefix counts",
             "480x640 B16": "32x60 prefix counts",
             "480x640 B32": "32x60 prefix counts",
             "480x640 B64": "32x120 nt prefix counts",
-            "720x1280 B128": "32x240 prefix counts",
+            "720x1280 B128": "32x240 reduce-then-scan",
             "720x1280 B16": "32x120 nt prefix counts",
-            "720x1280 B32": "32x240 nt reduce-then-scan",
-            "720x1280 B64": "64x240 nt reduce-then-scan"
+            "720x1280 B32": "32x240 nt prefix counts",
+            "720x1280 B64": "64x240 nt prefix counts"
         },
-        "fetch_bytes": 2268904034,
-        "write_bytes": 126806069856,
+        "fetch_bytes": 2265890098,
+        "write_bytes": 126814648608,
         "source": "profiles/uneven_batch_256_tile_pass_hbm_counters.md"
     }
 }

@@ -97,6 +97,71 @@ __device__ __forceinline__ void rowcarry_walk(const FrameArgs& f, const uint32_t
     }
 }
 
+// Bin of byte c of a loaded word w: floor(v B / 256) (kBinScaled), the same
+// as one bit-field extract when B = 2^k with k >= 1 (kBinShift; bs = 8 - k,
+// so 8 c + bs <= 31), the bin table staged in LDS (kBinTable), or either of
+// the first and the last as the frame has it (kBinAny).
+enum BinForm { kBinScaled, kBinShift, kBinTable, kBinAny };
+template <int BF>
+__device__ __forceinline__ uint32_t bin_in_word(const FrameArgs& f, const uint32_t* lutw, uint32_t w, int c,
+                                                uint32_t B, int bs)
+{
+    if constexpr (BF == kBinShift) {
+        return (w >> (8 * c + bs)) & (B - 1u);
+    } else {
+        const uint32_t v = (w >> (8 * c)) & 0xFFu;
+        if constexpr (BF == kBinTable) return (lutw[v >> 2] >> (8 * (v & 3u))) & 0xFFu;
+        else if constexpr (BF == kBinScaled) return (v * B) >> 8;
+        else return bin_of(f, lutw, v, B);
+    }
+}
+
+// The pixels [x0, x0 + npx) of a row added to the 8-bit counters of their
+// segments (one 16-byte chunk per lane and round, four rounds in flight),
+// compiled per bin form; whole chunks take no per-pixel bound check.
+template <int BF>
+__device__ __forceinline__ void rowcarry_count(const FrameArgs& f, const IH_GLOBAL uint8_t* prow, uint32_t* lds,
+                                               const uint32_t* lutw, int lane, int x0, int npx, bool vec, int bs)
+{
+    const Geom& g = f.g;
+    const uint32_t B = (uint32_t)g.B;
+    const int TX = g.TX;
+    const int nchunks = (npx + 15) / 16;
+    for (int c0 = 0; c0 < nchunks; c0 += 4 * kRowThreads) {
+        // up to four 16-byte chunks per lane in flight before any counting
+        u32x4 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * kRowThreads + lane;
+            const int p = c * 16;
+            if (c < nchunks && vec && p + 16 <= npx) {
+                w[u] = *reinterpret_cast<const IH_GLOBAL u32x4*>(prow + x0 + p);
+            } else {
+                uint32_t b4[4] = {0u, 0u, 0u, 0u};
+                for (int k = 0; c < nchunks && k < 16 && p + k < npx; ++k)
+                    b4[k / 4] |= (uint32_t)prow[x0 + p + k] << (8 * (k % 4));
+                w[u] = u32x4{b4[0], b4[1], b4[2], b4[3]};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * kRowThreads + lane;
+            if (c >= nchunks) continue;
+            const int p = c * 16;
+            const uint32_t seg = (uint32_t)((p / TX) * (int)B);
+            const uint32_t words[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+            if (p + 16 <= npx) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) lds_inc8(lds, seg + bin_in_word<BF>(f, lutw, words[k / 4], k % 4, B, bs));
+            } else {
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    if (p + k < npx) lds_inc8(lds, seg + bin_in_word<BF>(f, lutw, words[k / 4], k % 4, B, bs));
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uint32_t* lds)
 {
     const Geom& g = f.g;
@@ -113,45 +178,17 @@ __device__ __forceinline__ void rowcarry_body(const FrameArgs& f, int64_t y, uin
     // the bin table sits after the counters of the largest segment chunk
     uint32_t* lutw = lds + (((kSegChunk < g.nTX ? kSegChunk : g.nTX) * B + 3) / 4);
     stage_lut(f, lutw, lane, kRowThreads);      // visible after the first barrier below
+    const bool pow2 = B >= 2 && (B & (B - 1)) == 0;
+    const int bs = 8 - (31 - __builtin_clz((uint32_t)B));
     for (int j0 = 0; j0 < g.nTX; j0 += kSegChunk) {
         const int ns = min(kSegChunk, g.nTX - j0);
         for (int w = lane; w < (ns * B + 3) / 4; w += kRowThreads) lds[w] = 0u;
         wave_sync();
         const int x0 = j0 * TX;
         const int npx = min(ns * TX, g.W - x0);
-        const int nchunks = (npx + 15) / 16;
-        for (int c0 = 0; c0 < nchunks; c0 += 4 * kRowThreads) {
-            // up to four 16-byte chunks per lane in flight before any counting
-            u32x4 w[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + u * kRowThreads + lane;
-                const int p = c * 16;
-                if (c < nchunks && vec && p + 16 <= npx) {
-                    w[u] = *reinterpret_cast<const IH_GLOBAL u32x4*>(prow + x0 + p);
-                } else {
-                    uint32_t b4[4] = {0u, 0u, 0u, 0u};
-                    for (int k = 0; c < nchunks && k < 16 && p + k < npx; ++k)
-                        b4[k / 4] |= (uint32_t)prow[x0 + p + k] << (8 * (k % 4));
-                    w[u] = u32x4{b4[0], b4[1], b4[2], b4[3]};
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + u * kRowThreads + lane;
-                if (c >= nchunks) continue;
-                const int p = c * 16;
-                const uint32_t seg = (uint32_t)((p / TX) * B);
-                const uint32_t words[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    if (p + k < npx) {
-                        const uint32_t v = (words[k / 4] >> (8 * (k % 4))) & 0xFFu;
-                        lds_inc8(lds, seg + bin_of(f, lutw, v, (uint32_t)B));
-                    }
-                }
-            }
-        }
+        if (f.lut) rowcarry_count<kBinTable>(f, prow, lds, lutw, lane, x0, npx, vec, bs);
+        else if (pow2) rowcarry_count<kBinShift>(f, prow, lds, lutw, lane, x0, npx, vec, bs);
+        else rowcarry_count<kBinScaled>(f, prow, lds, lutw, lane, x0, npx, vec, bs);
         wave_sync();
         if (bpl == 1) {
             // one bin per lane: four segments at a time
@@ -224,24 +261,6 @@ __device__ __forceinline__ void col_inc(uint32_t* h, int cw, int sh, int x, uint
     else col_inc(h, cw, sh, x, b);
 }
 
-// Bin of byte c of a loaded word w: floor(v B / 256) (kBinScaled), the same
-// as one bit-field extract when B = 2^k with k >= 1 (kBinShift; bs = 8 - k,
-// so 8 c + bs <= 31), the bin table staged in LDS (kBinTable), or either of
-// the first and the last as the frame has it (kBinAny).
-enum BinForm { kBinScaled, kBinShift, kBinTable, kBinAny };
-template <int BF>
-__device__ __forceinline__ uint32_t bin_in_word(const FrameArgs& f, const uint32_t* lutw, uint32_t w, int c,
-                                                uint32_t B, int bs)
-{
-    if constexpr (BF == kBinShift) {
-        return (w >> (8 * c + bs)) & (B - 1u);
-    } else {
-        const uint32_t v = (w >> (8 * c)) & 0xFFu;
-        if constexpr (BF == kBinTable) return (lutw[v >> 2] >> (8 * (v & 3u))) & 0xFFu;
-        else if constexpr (BF == kBinScaled) return (v * B) >> 8;
-        else return bin_of(f, lutw, v, B);
-    }
-}
 __device__ __forceinline__ uint32_t col_get(const uint32_t* h, int cw, int sh, int x, int b)
 {
     const uint32_t w = h[x * cw + (b >> sh)];
